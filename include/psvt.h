@@ -1,0 +1,131 @@
+/*
+ * psvt -- singular value soft-thresholding through the polar decomposition,
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Operation (section 2 of the paper, Eq. (1)): for A = U Sigma V^T,
+ *     A_tau = U max(Sigma - tau I, 0) V^T.
+ * Proposition 1 computes it without an SVD: with P = polar(A) and
+ * S = polar(A^T A - tau^2 I),  A_tau = (A + A S)/2 - tau/2 (P + P S),
+ * or, from the footnote, with S = polar(A A^T - tau^2 I),
+ *     A_tau = (S A + A)/2 - tau/2 (S P + P).
+ * (The proposition prints the shift as tau I; the proof requires
+ * sign(sigma^2 - c) = sign(sigma - tau), i.e. c = tau^2, and the paper's code
+ * listing shifts by tau**2.  This library shifts by tau^2.)
+ * Both polar factors come from matmul-only odd-quintic iterations
+ * (Newton-Schulz / Polar-Express type, sections 1 and 3).  The library
+ * evaluates the proposition in the fused form A_tau = (A - tau P)(I + S)/2,
+ * which is the same expression regrouped.
+ *
+ * Conventions for every entry point
+ *   - Matrices are float32, row-major; ld* is the row stride in elements and
+ *     must be >= the column count.  Matrix pointers are DEVICE pointers owned
+ *     by the caller; inputs are read only, outputs are written only.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *     enqueues work on `stream` and returns: no host synchronisation, no device
+ *     allocation, no device-to-host read.  Results are ready when the stream
+ *     reaches that point.
+ *   - `ws` is caller-owned device scratch of at least psvt_workspace_bytes()
+ *     bytes, 256-byte aligned; its contents need not be initialised and are
+ *     garbage afterwards.  Calls that overlap in time must not share `ws`.
+ *   - `cfg` may be NULL (all defaults).  A zero-initialised psvt_config means
+ *     defaults too.
+ *   - Return value: PSVT_OK or a negative PSVT_E* code; the argument checks
+ *     run on the host before anything is enqueued, so on error nothing was
+ *     launched.  psvt_last_error() gives a thread-local message.
+ *   - m == 0 or n == 0 is a valid no-op.
+ *   - Outputs must not overlap inputs or `ws` (PSVT_EINVAL when they do).
+ */
+#ifndef PSVT_H
+#define PSVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PSVT_OK = 0,
+    PSVT_EINVAL = -1,       /* bad argument */
+    PSVT_EWORKSPACE = -2,   /* ws NULL or smaller than psvt_workspace_bytes() */
+    PSVT_EUNSUPPORTED = -3, /* current device is not gfx950 */
+    PSVT_EHIP = -4          /* a HIP call or kernel launch failed */
+};
+
+/* operation ids for psvt_workspace_bytes */
+enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R = 3 };
+
+/* side selection (Proposition 1 and its footnote) */
+enum { PSVT_SIDE_AUTO = 0, PSVT_SIDE_RIGHT = 1, PSVT_SIDE_LEFT = 2 };
+
+typedef struct psvt_config {
+    /* Polar iterations per polar factor (the paper recommends 20, section 3;
+     * its listing defaults to 11).  0 means 20.  Range 1..256. */
+    int32_t iters;
+    /* Precision schedule: the first n_fp8 iterations use FP8 (OCP e4m3)
+     * operands, the next n_bf16 use BF16 operands, the rest FP32; all
+     * accumulate in FP32 and keep an FP32 iterate.  n_fp8 + n_bf16 <= iters.
+     * The Gram matrix and the final product are always FP32. */
+    int32_t n_fp8;
+    int32_t n_bf16;
+    /* PSVT_SIDE_AUTO follows the paper's listing: right-sided (A^T A) when
+     * n < m, else left-sided (A A^T). */
+    int32_t side;
+    /* Optional host array of iters x 3 quintic coefficients (a, b, c) that
+     * replaces the built-in schedule (the paper's listing lets the caller
+     * inject the polar algorithm).  Read during the call only. */
+    const double *coeffs;
+    uint32_t flags; /* reserved, must be 0 */
+    int32_t reserved[3];
+} psvt_config;
+
+/* Workspace size for `op` on an m x n input (for PSVT_OP_POLAR_SYM, m = n). */
+int psvt_workspace_bytes(int op, int64_t m, int64_t n, const psvt_config *cfg, size_t *bytes);
+
+/* Y = A_tau (Eq. (1)) via Proposition 1.  A: m x n (lda), Y: m x n (ldy).
+ * tau must be finite and >= 0.  tau = 0 gives A (up to the iterations'
+ * accuracy); tau >= sigma_max gives 0. */
+int psvt_svt(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy, void *ws,
+             size_t ws_bytes, const psvt_config *cfg, void *stream);
+
+/* P = polar(A) = U V^T (section 2).  A: m x n (lda), P: m x n (ldp).  For a
+ * rank-deficient A the iterations converge to the partial isometry over the
+ * nonzero singular values. */
+int psvt_polar(const float *A, int64_t m, int64_t n, int64_t lda, float *P, int64_t ldp, void *ws, size_t ws_bytes,
+               const psvt_config *cfg, void *stream);
+
+/* S = polar(G) for symmetric G, i.e. the matrix sign of its eigenvalues
+ * (section 2).  G: n x n (ldg), symmetrised on load as (G + G^T)/2.
+ * S: n x n (lds).  Zero eigenvalues map to 0. */
+int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds, void *ws, size_t ws_bytes,
+                   const psvt_config *cfg, void *stream);
+
+/* Best rank-r approximation [A]_r (Corollary 1): with S = polar(A^T A -
+ * tau^2 I), [A]_r = (A + A S)/2 = A (I + S)/2 (left-sided form for wide A).
+ * tau must lie strictly between sigma_{r+1} and sigma_r (descending order). */
+int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy, void *ws,
+                size_t ws_bytes, const psvt_config *cfg, void *stream);
+
+/* Building block exposed for kernel-level tests: the FP32 MFMA product
+ *     C[i][j] = alpha * sum_k A[i][k] B[j][k] + beta * D[i][j]
+ * (A: M x K, B: N x K, C, D: M x N; all row-major, device, ld multiple of 4,
+ * 16-byte aligned).  D may be NULL (beta ignored).  sym != 0 requires M == N
+ * and computes only the lower block triangle, mirroring it into the upper
+ * one (valid when the product is symmetric, e.g. A = B). */
+int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const float *D, int64_t ldd, float *C,
+                 int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym, void *stream);
+
+/* Static description of a return code. */
+const char *psvt_strerror(int code);
+
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char *psvt_last_error(void);
+
+/* Library version string. */
+const char *psvt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSVT_H */

@@ -1,1 +1,247 @@
-"""Singular value soft-thresholding through the polar decomposition, on MI355X."""
+"""Singular value soft-thresholding through the polar decomposition, on
+AMD MI355X (gfx950).
+
+Thin Python binding over ``libpsvt.so`` (C ABI in ``include/psvt.h``).  The
+functions here only marshal arguments: check shapes and dtypes, allocate the
+output and workspace with torch on the current HIP device, and pass raw
+device pointers and the current stream to the library.  Every step of the
+computation runs in the library's kernels.  There is no fallback: without the
+built library or a gfx950 device the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsvt.so")
+
+PSVT_OK = 0
+PSVT_EINVAL = -1
+PSVT_EWORKSPACE = -2
+PSVT_EUNSUPPORTED = -3
+PSVT_EHIP = -4
+
+OP_SVT, OP_POLAR, OP_POLAR_SYM, OP_RANK_R = 0, 1, 2, 3
+SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
+
+EXPORTED = [
+    "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt",
+    "psvt_strerror", "psvt_last_error", "psvt_version",
+]
+
+
+class PsvtError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__("%s failed (%d): %s" % (where, code, detail))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    """Mirror of ``psvt_config``."""
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("n_fp8", ctypes.c_int32),
+        ("n_bf16", ctypes.c_int32),
+        ("side", ctypes.c_int32),
+        ("coeffs", ctypes.POINTER(ctypes.c_double)),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load ``libpsvt.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError("libpsvt.so is not built (run python -m paper_2607_22484_amd.build)")
+    lib = ctypes.CDLL(path)
+    i64, vp, f64 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double
+    cfgp = ctypes.POINTER(Config)
+    lib.psvt_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, cfgp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.psvt_svt.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
+    lib.psvt_rank_r.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
+    lib.psvt_polar.argtypes = [vp, i64, i64, i64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
+    lib.psvt_polar_sym.argtypes = [vp, i64, i64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
+    lib.psvt_gemm_nt.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_int, vp]
+    for f in ("psvt_workspace_bytes", "psvt_svt", "psvt_rank_r", "psvt_polar", "psvt_polar_sym", "psvt_gemm_nt"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.psvt_strerror.argtypes = [ctypes.c_int]
+    lib.psvt_strerror.restype = ctypes.c_char_p
+    lib.psvt_last_error.restype = ctypes.c_char_p
+    lib.psvt_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != PSVT_OK:
+        lib = load()
+        raise PsvtError(rc, where, (lib.psvt_last_error() or b"").decode() or lib.psvt_strerror(rc).decode())
+
+
+def make_config(iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
+                coeffs: Optional[Sequence[float]] = None):
+    cfg = Config()
+    cfg.iters = int(iters)
+    cfg.n_fp8 = int(n_fp8)
+    cfg.n_bf16 = int(n_bf16)
+    cfg.side = int(side)
+    keep = None
+    if coeffs is not None:
+        keep = (ctypes.c_double * len(coeffs))(*[float(c) for c in coeffs])
+        cfg.coeffs = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+    return cfg, keep
+
+
+def workspace_bytes(op: int, m: int, n: int, cfg: Optional[Config] = None) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().psvt_workspace_bytes(op, m, n, ctypes.byref(cfg) if cfg is not None else None,
+                                       ctypes.byref(out)), "psvt_workspace_bytes")
+    return int(out.value)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_input(A, name="A"):
+    torch = _torch()
+    if not isinstance(A, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if A.ndim != 2:
+        raise ValueError("input tensor must be 2D")
+    if A.dtype != torch.float32:
+        raise TypeError("%s must be float32" % name)
+    if A.device.type != "cuda":
+        raise TypeError("%s must live on the GPU" % name)
+    if A.stride(1) != 1 and A.numel() > 0:
+        raise ValueError("%s must be row-major with unit column stride" % name)
+
+
+def _stream_ptr(A):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(A.device).cuda_stream)
+
+
+def _workspace(op, m, n, cfg, device, ws=None):
+    torch = _torch()
+    need = workspace_bytes(op, m, n, cfg)
+    if ws is not None:
+        if ws.numel() * ws.element_size() < need:
+            raise ValueError("workspace too small: %d < %d bytes" % (ws.numel() * ws.element_size(), need))
+        return ws, need
+    return torch.empty(max(need, 256), dtype=torch.uint8, device=device), need
+
+
+def _ld(A):
+    """Row stride in elements.  A one-row tensor's stride is never stepped
+    over, so any value >= the column count is valid; use a multiple of 4."""
+    if A.shape[0] > 1:
+        return A.stride(0)
+    cols = max(A.shape[1], 1)
+    return A.stride(0) if A.stride(0) >= cols and A.stride(0) % 4 == 0 else (cols + 3) // 4 * 4
+
+
+def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
+        coeffs=None, out=None, ws=None):
+    """A_tau = U max(Sigma - tau I, 0) V^T via Proposition 1 (FP32 out)."""
+    _check_input(A)
+    torch = _torch()
+    m, n = A.shape
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs)
+    Y = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
+    if m == 0 or n == 0:
+        return Y
+    buf, need = _workspace(OP_SVT, m, n, cfg, A.device, ws)
+    with torch.cuda.device(A.device):
+        _check(load().psvt_svt(A.data_ptr(), m, n, _ld(A), float(tau), Y.data_ptr(), _ld(Y), buf.data_ptr(), need,
+                               ctypes.byref(cfg), _stream_ptr(A)), "psvt_svt")
+    del keep
+    return Y
+
+
+def rank_r(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
+           coeffs=None, out=None, ws=None):
+    """Best rank-r approximation (Corollary 1), tau between sigma_{r+1} and sigma_r."""
+    _check_input(A)
+    torch = _torch()
+    m, n = A.shape
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs)
+    Y = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
+    if m == 0 or n == 0:
+        return Y
+    buf, need = _workspace(OP_RANK_R, m, n, cfg, A.device, ws)
+    with torch.cuda.device(A.device):
+        _check(load().psvt_rank_r(A.data_ptr(), m, n, _ld(A), float(tau), Y.data_ptr(), _ld(Y), buf.data_ptr(),
+                                  need, ctypes.byref(cfg), _stream_ptr(A)), "psvt_rank_r")
+    del keep
+    return Y
+
+
+def polar(A, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO, coeffs=None, out=None,
+          ws=None):
+    """Polar factor U V^T (section 2)."""
+    _check_input(A)
+    torch = _torch()
+    m, n = A.shape
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs)
+    P = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
+    if m == 0 or n == 0:
+        return P
+    buf, need = _workspace(OP_POLAR, m, n, cfg, A.device, ws)
+    with torch.cuda.device(A.device):
+        _check(load().psvt_polar(A.data_ptr(), m, n, _ld(A), P.data_ptr(), _ld(P), buf.data_ptr(), need,
+                                 ctypes.byref(cfg), _stream_ptr(A)), "psvt_polar")
+    del keep
+    return P
+
+
+def polar_sym(G, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, coeffs=None, out=None, ws=None):
+    """Matrix sign of symmetric G (symmetrised on load)."""
+    _check_input(G, "G")
+    torch = _torch()
+    n, n2 = G.shape
+    if n != n2:
+        raise ValueError("polar_sym needs a square matrix")
+    cfg, keep = make_config(iters, n_fp8, n_bf16, SIDE_AUTO, coeffs)
+    S = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=G.device)
+    if n == 0:
+        return S
+    buf, need = _workspace(OP_POLAR_SYM, n, n, cfg, G.device, ws)
+    with torch.cuda.device(G.device):
+        _check(load().psvt_polar_sym(G.data_ptr(), n, _ld(G), S.data_ptr(), _ld(S), buf.data_ptr(), need,
+                                     ctypes.byref(cfg), _stream_ptr(G)), "psvt_polar_sym")
+    del keep
+    return S
+
+
+def gemm_nt(A, B, D=None, alpha: float = 1.0, beta: float = 0.0, sym: bool = False, out=None):
+    """C = alpha A B^T + beta D with the library's FP32 MFMA kernel."""
+    torch = _torch()
+    _check_input(A)
+    _check_input(B, "B")
+    M, K = A.shape
+    N, K2 = B.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    C = out if out is not None else torch.empty((M, N), dtype=torch.float32, device=A.device)
+    dptr, ldd = (D.data_ptr(), _ld(D)) if D is not None else (None, 0)
+    with torch.cuda.device(A.device):
+        _check(load().psvt_gemm_nt(A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), dptr, ldd, C.data_ptr(), _ld(C),
+                                   M, N, K, float(alpha), float(beta), 1 if sym else 0, _stream_ptr(A)),
+               "psvt_gemm_nt")
+    return C
+
+
+def version() -> str:
+    return load().psvt_version().decode()

@@ -1,0 +1,602 @@
+// Host side of the C ABI declared in include/psvt.h: argument checks,
+// workspace layout and the launch plan of each operation.
+//
+// Orientation.  Every operation works on an l x s iterate X whose Gram
+// matrix X^T X is s x s.  Right-sided (Proposition 1): X = A, s = n.
+// Left-sided (footnote of Proposition 1): X = A^T, s = m; then
+// A_tau = (A^T)_tau^T, so the left-sided formula is the right-sided one on
+// the transposed matrix and only the final write is transposed.
+//
+// Plan of psvt_svt (all on the caller's stream, scalars stay on the device):
+//   nu    = ||A||_F (FP64)                         -> scale into the unit ball
+//   X0    = X/nu and X0^T (one tiled pass over A)
+//   T     = X0^T X0                       (half-flop symmetric product)
+//   theta_P = sqrt(||T||_F) >= sigma_max(X0)       (FP64)
+//   H     = T - (tau/nu)^2 I              (diagonal shift in FP64)
+//   R     = H H,  theta_S = sqrt(||R||_F) >= |lambda|_max(H)
+//   P     : K odd-quintic iterations X <- X (a I + b X^T X + c (X^T X)^2)
+//           (the first one applies 1/theta_P through device scalars)
+//   S     : K iterations X <- a X + (b X^2 + c X^4) X on symmetric X,
+//           starting from H / theta_S; the last one writes Pi = (I + S)/2
+//   Y     = (nu X0 - tau P) Pi   (= (A - tau P)(I + S)/2, written transposed
+//           for the left-sided case)
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/psvt.h"
+#include "coeffs.h"
+#include "kernels.h"
+
+using namespace psvt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(PSVT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// ------------------------------------------------------------ device check
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_dev_once[kMaxDevices];
+int g_dev_ok[kMaxDevices];
+
+int check_device() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(PSVT_EUNSUPPORTED, "device index %d out of range", dev);
+    std::call_once(g_dev_once[dev], [dev]() {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            g_dev_ok[dev] = -1;
+            return;
+        }
+        g_dev_ok[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    });
+    if (g_dev_ok[dev] == 1) return PSVT_OK;
+    return fail(PSVT_EUNSUPPORTED, "device %d is not gfx950", dev);
+}
+
+// ------------------------------------------------------------- config
+
+struct Cfg {
+    int iters;
+    int n_fp8, n_bf16;
+    int side;
+    const double *coeffs;
+};
+
+int read_cfg(const psvt_config *c, Cfg &out) {
+    out.iters = 20;
+    out.n_fp8 = out.n_bf16 = 0;
+    out.side = PSVT_SIDE_AUTO;
+    out.coeffs = nullptr;
+    if (!c) return PSVT_OK;
+    if (c->iters < 0 || c->iters > 256) return fail(PSVT_EINVAL, "iters = %d outside 0..256", c->iters);
+    if (c->iters) out.iters = c->iters;
+    if (c->n_fp8 < 0 || c->n_bf16 < 0 || (int64_t)c->n_fp8 + c->n_bf16 > out.iters)
+        return fail(PSVT_EINVAL, "n_fp8 = %d, n_bf16 = %d do not fit in %d iterations", c->n_fp8, c->n_bf16,
+                    out.iters);
+    if (c->side < 0 || c->side > 2) return fail(PSVT_EINVAL, "side = %d", c->side);
+    if (c->flags != 0) return fail(PSVT_EINVAL, "flags must be 0");
+    out.n_fp8 = c->n_fp8;
+    out.n_bf16 = c->n_bf16;
+    out.side = c->side;
+    out.coeffs = c->coeffs;
+    if (out.coeffs)
+        for (int i = 0; i < 3 * out.iters; ++i)
+            if (!isfinite(out.coeffs[i])) return fail(PSVT_EINVAL, "coeffs[%d] is not finite", i);
+    if (out.n_fp8 || out.n_bf16) return fail(PSVT_EUNSUPPORTED, "low-precision iterations are not available");
+    return PSVT_OK;
+}
+
+void coef(const Cfg &c, int t, float &a, float &b, float &cc) {
+    const double *p = c.coeffs ? c.coeffs + 3 * t : psvt_coeff_table[t < PSVT_COEFF_LEN ? t : PSVT_COEFF_LEN - 1];
+    a = (float)p[0];
+    b = (float)p[1];
+    cc = (float)p[2];
+}
+
+// ---------------------------------------------------------- workspace
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+struct Layout {
+    int64_t l = 0, s = 0, ldL = 0, ldS = 0;
+    bool right = true;
+    size_t scal = 0, part = 0;
+    size_t X0 = 0, X0T = 0, Xp = 0, Xq = 0, XTp = 0, XTq = 0;
+    size_t T = 0, Bm = 0;
+    size_t H = 0, R = 0, S0 = 0, S1 = 0, X2 = 0, BS = 0;
+    size_t total = 0;
+};
+
+// right-sided iff n < m in auto mode (the listing's rule; square -> left)
+bool choose_right(int side, int64_t m, int64_t n) {
+    if (side == PSVT_SIDE_RIGHT) return true;
+    if (side == PSVT_SIDE_LEFT) return false;
+    return n < m;
+}
+
+Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c) {
+    Layout L;
+    if (op == PSVT_OP_POLAR_SYM) {
+        L.right = true;
+        L.l = L.s = n;
+    } else if (op == PSVT_OP_POLAR) {
+        // polar(A^T) = polar(A)^T: iterate on the tall orientation
+        L.right = c.side == PSVT_SIDE_AUTO ? (m >= n) : choose_right(c.side, m, n);
+        L.l = L.right ? m : n;
+        L.s = L.right ? n : m;
+    } else {
+        L.right = choose_right(c.side, m, n);
+        L.l = L.right ? m : n;
+        L.s = L.right ? n : m;
+    }
+    L.ldL = round_up(L.l, 64);
+    L.ldS = round_up(L.s, 64);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += (size_t)round_up((int64_t)bytes, 256);
+        return o;
+    };
+    const size_t fS = sizeof(float) * (size_t)L.s * L.ldS;  // s x s
+    const size_t fX = sizeof(float) * (size_t)L.l * L.ldS;  // l x s
+    const size_t fXT = sizeof(float) * (size_t)L.s * L.ldL; // s x l
+    L.scal = take(sizeof(Scalars));
+    L.part = take(sizeof(double) * NORM_PARTIALS);
+    const bool need_P = op == PSVT_OP_SVT || op == PSVT_OP_POLAR;
+    const bool need_S = op != PSVT_OP_POLAR;
+    if (op != PSVT_OP_POLAR_SYM) {
+        L.X0 = take(fX);
+        L.X0T = take(fXT);
+        L.T = take(fS);
+    }
+    if (need_P) {
+        L.Xp = take(fX);
+        L.Xq = take(fX);
+        L.XTp = take(fXT);
+        L.XTq = take(fXT);
+        L.Bm = take(fS);
+    }
+    if (need_S) {
+        L.H = take(fS);
+        L.R = take(fS);
+        L.S0 = take(fS);
+        L.S1 = take(fS);
+        L.X2 = take(fS);
+        L.BS = take(fS);
+    }
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------------ checks
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+size_t span_bytes(int64_t rows, int64_t cols, int64_t ld) {
+    return rows <= 0 || cols <= 0 ? 0 : sizeof(float) * (size_t)((rows - 1) * ld + cols);
+}
+
+int check_matrix(const void *p, int64_t rows, int64_t cols, int64_t ld, const char *name) {
+    if (rows < 0 || cols < 0) return fail(PSVT_EINVAL, "%s: negative size %lld x %lld", name, (long long)rows,
+                                          (long long)cols);
+    if (rows == 0 || cols == 0) return PSVT_OK;
+    if (!p) return fail(PSVT_EINVAL, "%s is NULL", name);
+    if (ld < cols) return fail(PSVT_EINVAL, "%s: ld = %lld < %lld columns", name, (long long)ld, (long long)cols);
+    if (rows > (1LL << 30) || cols > (1LL << 30)) return fail(PSVT_EINVAL, "%s: dimension too large", name);
+    return PSVT_OK;
+}
+
+// ------------------------------------------------------------- helpers
+
+GemmArgs gemm_defaults() {
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    g.alpha = 1.0f;
+    g.wa = 1.0f;
+    g.ab_scale = 1.0f;
+    g.lp_scale = 1.0f;
+    g.i_alpha = g.i_beta = g.i_wa = g.i_wa2 = -1;
+    return g;
+}
+
+char *at(void *ws, size_t off) { return (char *)ws + off; }
+float *F(void *ws, size_t off) { return (float *)at(ws, off); }
+
+// symmetric product C = alpha A B^T + beta D (+ diag I), A, B, C, D s x s
+hipError_t syrk(const float *A, const float *B, int64_t ld, const float *D, float *C, int64_t ldc, int64_t s,
+                float alpha, int i_alpha, float beta, int i_beta, float diag, const Scalars *sc, hipStream_t st) {
+    GemmArgs g = gemm_defaults();
+    g.A = A;
+    g.B = B;
+    g.lda = g.ldb = ld;
+    g.D = D;
+    g.ldd = ld;
+    g.C = C;
+    g.ldc = ldc;
+    g.M = g.N = (int)s;
+    g.K = (int)s;
+    g.alpha = alpha;
+    g.i_alpha = i_alpha;
+    g.beta = beta;
+    g.i_beta = i_beta;
+    g.diag = diag;
+    g.sc = sc;
+    g.sym = 1;
+    return launch_gemm(g, OP_F32, st);
+}
+
+// Gram prelude shared by svt / polar / rank_r: nu, X0, X0^T, T, theta_P.
+int prelude(const float *A, int64_t m, int64_t n, int64_t lda, double tau, const Layout &L, void *ws,
+            hipStream_t st, bool want_theta_p) {
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    double *part = (double *)at(ws, L.part);
+    HIP_TRY(launch_fro_norm(A, m, n, lda, part, sc, NORM_INPUT, tau, st), "norm of A");
+    float *X0 = F(ws, L.X0), *X0T = F(ws, L.X0T);
+    // right: X = A -> X0 = A/nu (copy), X0T = A^T/nu; left: X = A^T -> swapped
+    if (L.right)
+        HIP_TRY(launch_scale_transpose(A, m, n, lda, X0, L.ldS, X0T, L.ldL, sc, F_INV_NU, st), "scale A");
+    else
+        HIP_TRY(launch_scale_transpose(A, m, n, lda, X0T, L.ldL, X0, L.ldS, sc, F_INV_NU, st), "scale A");
+    // T = X0^T X0 = (X0^T)(X0^T)^T : NT product of the s x l transposed copy
+    GemmArgs g = gemm_defaults();
+    g.A = X0T;
+    g.B = X0T;
+    g.lda = g.ldb = L.ldL;
+    g.C = F(ws, L.T);
+    g.ldc = L.ldS;
+    g.M = g.N = (int)L.s;
+    g.K = (int)L.l;
+    g.sc = sc;
+    g.sym = 1;
+    HIP_TRY(launch_gemm(g, OP_F32, st), "Gram");
+    if (want_theta_p)
+        HIP_TRY(launch_fro_norm(F(ws, L.T), L.s, L.s, L.ldS, part, sc, NORM_THETA_P, 0.0, st), "theta_P");
+    return PSVT_OK;
+}
+
+// P iterations.  Result in *out_P (workspace, l x s, ld = ldS) or, when
+// user_out is given, the last iteration writes straight to the caller's
+// buffer (transposed when !L.right).
+int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, float *user_out, int64_t ld_out,
+                     const float **out_P) {
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    const float *curX = F(ws, L.X0), *curXT = F(ws, L.X0T);
+    float *bufX[2] = {F(ws, L.Xp), F(ws, L.Xq)};
+    float *bufXT[2] = {F(ws, L.XTp), F(ws, L.XTq)};
+    float *T = F(ws, L.T), *Bm = F(ws, L.Bm);
+    for (int t = 0; t < c.iters; ++t) {
+        float a, b, cc;
+        coef(c, t, a, b, cc);
+        const bool first = t == 0, last = t == c.iters - 1;
+        if (!first) {
+            GemmArgs g = gemm_defaults();
+            g.A = curXT;
+            g.B = curXT;
+            g.lda = g.ldb = L.ldL;
+            g.C = T;
+            g.ldc = L.ldS;
+            g.M = g.N = (int)L.s;
+            g.K = (int)L.l;
+            g.sc = sc;
+            g.sym = 1;
+            HIP_TRY(launch_gemm(g, OP_F32, st), "P: X^T X");
+        }
+        // Bm = c T^2 + b T   (first iteration: T / theta^2 scaling folded in)
+        HIP_TRY(syrk(T, T, L.ldS, T, Bm, L.ldS, L.s, cc, first ? F_P4 : -1, b, first ? F_P2 : -1, 0.0f, sc, st),
+                "P: b T + c T^2");
+        // X' = a X + X Bm   (first iteration: times 1/theta)
+        GemmArgs g = gemm_defaults();
+        g.A = curX;
+        g.B = Bm;
+        g.lda = L.ldS;
+        g.ldb = L.ldS;
+        g.D = curX;
+        g.ldd = L.ldS;
+        g.M = (int)L.l;
+        g.N = (int)L.s;
+        g.K = (int)L.s;
+        g.alpha = 1.0f;
+        g.i_alpha = first ? F_P1 : -1;
+        g.beta = a;
+        g.i_beta = first ? F_P1 : -1;
+        g.sc = sc;
+        float *nX = bufX[t & 1], *nXT = bufXT[t & 1];
+        if (last && user_out) {
+            if (L.right) {
+                g.C = user_out;
+                g.ldc = ld_out;
+            } else {
+                g.CT = user_out;
+                g.ldct = ld_out;
+            }
+        } else {
+            g.C = nX;
+            g.ldc = L.ldS;
+            if (!last) {
+                g.CT = nXT;
+                g.ldct = L.ldL;
+            }
+        }
+        HIP_TRY(launch_gemm(g, OP_F32, st), "P: a X + X B");
+        curX = nX;
+        curXT = nXT;
+    }
+    if (out_P) *out_P = curX;
+    return PSVT_OK;
+}
+
+// S iterations from H (s x s, ld = ldS) with R = H^2 and theta_S already in
+// the scalar block.  want_pi: the last iteration writes (I + S)/2.
+int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, bool want_pi, float *user_out,
+                    int64_t ld_out, const float **out_S) {
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    const int64_t s = L.s, ld = L.ldS;
+    const float *cur = F(ws, L.H);
+    float *R = F(ws, L.R), *X2 = F(ws, L.X2), *BS = F(ws, L.BS);
+    float *buf[2] = {F(ws, L.S0), F(ws, L.S1)};
+    for (int t = 0; t < c.iters; ++t) {
+        float a, b, cc;
+        coef(c, t, a, b, cc);
+        const bool first = t == 0, last = t == c.iters - 1;
+        const float *sq = R;
+        if (!first) {
+            HIP_TRY(syrk(cur, cur, ld, nullptr, X2, ld, s, 1.0f, -1, 0.0f, -1, 0.0f, sc, st), "S: X^2");
+            sq = X2;
+        }
+        HIP_TRY(syrk(sq, sq, ld, sq, BS, ld, s, cc, first ? F_S4 : -1, b, first ? F_S2 : -1, 0.0f, sc, st),
+                "S: b X^2 + c X^4");
+        float alpha = 1.0f, beta = a, diag = 0.0f;
+        if (last && want_pi) {
+            alpha = 0.5f;
+            beta = 0.5f * a;
+            diag = 0.5f;
+        }
+        float *dst = (last && user_out) ? user_out : buf[t & 1];
+        const int64_t ldd = (last && user_out) ? ld_out : ld;
+        HIP_TRY(syrk(BS, cur, ld, cur, dst, ldd, s, alpha, first ? F_S1 : -1, beta, first ? F_S1 : -1, diag, sc, st),
+                "S: a X + B X");
+        cur = dst;
+    }
+    if (out_S) *out_S = cur;
+    return PSVT_OK;
+}
+
+// H = T - (tau/nu)^2 I, R = H^2, theta_S
+int shifted_gram(const Layout &L, void *ws, hipStream_t st) {
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    double *part = (double *)at(ws, L.part);
+    HIP_TRY(launch_shift_copy(F(ws, L.T), L.s, L.ldS, F(ws, L.H), L.ldS, sc, st), "shift");
+    HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, L.s, 1.0f, -1, 0.0f, -1, 0.0f, sc, st),
+            "H^2");
+    HIP_TRY(launch_fro_norm(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_THETA_S, 0.0, st), "theta_S");
+    return PSVT_OK;
+}
+
+// Y = (nu X0 [- tau P]) Pi, written transposed for the left-sided case.
+int final_product(const Layout &L, void *ws, const float *P, double tau, const float *Pi, float *Y, int64_t ldy,
+                  hipStream_t st) {
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    GemmArgs g = gemm_defaults();
+    g.A = F(ws, L.X0);
+    g.lda = L.ldS;
+    g.wa = 1.0f;
+    g.i_wa = F_NU;
+    if (P) {
+        g.A2 = P;
+        g.lda2 = L.ldS;
+        g.wa2 = (float)(-tau);
+    }
+    g.B = Pi;
+    g.ldb = L.ldS;
+    g.M = (int)L.l;
+    g.N = (int)L.s;
+    g.K = (int)L.s;
+    g.sc = sc;
+    if (L.right) {
+        g.C = Y;
+        g.ldc = ldy;
+    } else {
+        g.CT = Y;
+        g.ldct = ldy;
+    }
+    HIP_TRY(launch_gemm(g, OP_F32, st), "final product");
+    return PSVT_OK;
+}
+
+int check_ws(void *ws, size_t ws_bytes, const Layout &L) {
+    if (!ws) return fail(PSVT_EWORKSPACE, "workspace is NULL");
+    if (ws_bytes < L.total)
+        return fail(PSVT_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    if (((uintptr_t)ws & 255) != 0) return fail(PSVT_EINVAL, "workspace is not 256-byte aligned");
+    return PSVT_OK;
+}
+
+int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
+             void *ws, size_t ws_bytes, const psvt_config *cfg, void *stream) {
+    g_last_error.clear();
+    Cfg c;
+    int rc = read_cfg(cfg, c);
+    if (rc) return rc;
+    if ((rc = check_matrix(A, m, n, lda, "A"))) return rc;
+    if ((rc = check_matrix(Y, m, n, ldy, "Y"))) return rc;
+    if (!(tau >= 0.0) || !isfinite(tau)) return fail(PSVT_EINVAL, "tau must be finite and >= 0");
+    if (m == 0 || n == 0) return PSVT_OK;
+    Layout L = make_layout(op, m, n, c);
+    if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+    if (overlaps(Y, span_bytes(m, n, ldy), A, span_bytes(m, n, lda)) ||
+        overlaps(Y, span_bytes(m, n, ldy), ws, L.total) || overlaps(A, span_bytes(m, n, lda), ws, L.total))
+        return fail(PSVT_EINVAL, "Y, A and ws must not overlap");
+    if ((rc = check_device())) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = prelude(A, m, n, lda, tau, L, ws, st, op == PSVT_OP_SVT))) return rc;
+    if ((rc = shifted_gram(L, ws, st))) return rc;
+    const float *P = nullptr, *Pi = nullptr;
+    if (op == PSVT_OP_SVT)
+        if ((rc = polar_iterations(c, L, ws, st, nullptr, 0, &P))) return rc;
+    if ((rc = sign_iterations(c, L, ws, st, true, nullptr, 0, &Pi))) return rc;
+    return final_product(L, ws, P, tau, Pi, Y, ldy, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+int psvt_workspace_bytes(int op, int64_t m, int64_t n, const psvt_config *cfg, size_t *bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(PSVT_EINVAL, "bytes is NULL");
+    if (op < PSVT_OP_SVT || op > PSVT_OP_RANK_R) return fail(PSVT_EINVAL, "unknown op %d", op);
+    if (m < 0 || n < 0) return fail(PSVT_EINVAL, "negative size");
+    if (op == PSVT_OP_POLAR_SYM && m != n) return fail(PSVT_EINVAL, "polar_sym needs m == n");
+    Cfg c;
+    int rc = read_cfg(cfg, c);
+    if (rc) return rc;
+    if (m == 0 || n == 0) {
+        *bytes = 0;
+        return PSVT_OK;
+    }
+    *bytes = make_layout(op, m, n, c).total;
+    return PSVT_OK;
+}
+
+int psvt_svt(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy, void *ws,
+             size_t ws_bytes, const psvt_config *cfg, void *stream) {
+    return svt_like(PSVT_OP_SVT, A, m, n, lda, tau, Y, ldy, ws, ws_bytes, cfg, stream);
+}
+
+int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy, void *ws,
+                size_t ws_bytes, const psvt_config *cfg, void *stream) {
+    return svt_like(PSVT_OP_RANK_R, A, m, n, lda, tau, Y, ldy, ws, ws_bytes, cfg, stream);
+}
+
+int psvt_polar(const float *A, int64_t m, int64_t n, int64_t lda, float *P, int64_t ldp, void *ws, size_t ws_bytes,
+               const psvt_config *cfg, void *stream) {
+    g_last_error.clear();
+    Cfg c;
+    int rc = read_cfg(cfg, c);
+    if (rc) return rc;
+    if ((rc = check_matrix(A, m, n, lda, "A"))) return rc;
+    if ((rc = check_matrix(P, m, n, ldp, "P"))) return rc;
+    if (m == 0 || n == 0) return PSVT_OK;
+    Layout L = make_layout(PSVT_OP_POLAR, m, n, c);
+    if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+    if (overlaps(P, span_bytes(m, n, ldp), A, span_bytes(m, n, lda)) ||
+        overlaps(P, span_bytes(m, n, ldp), ws, L.total) || overlaps(A, span_bytes(m, n, lda), ws, L.total))
+        return fail(PSVT_EINVAL, "P, A and ws must not overlap");
+    if ((rc = check_device())) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = prelude(A, m, n, lda, 0.0, L, ws, st, true))) return rc;
+    return polar_iterations(c, L, ws, st, P, ldp, nullptr);
+}
+
+int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds, void *ws, size_t ws_bytes,
+                   const psvt_config *cfg, void *stream) {
+    g_last_error.clear();
+    Cfg c;
+    int rc = read_cfg(cfg, c);
+    if (rc) return rc;
+    if ((rc = check_matrix(G, n, n, ldg, "G"))) return rc;
+    if ((rc = check_matrix(S, n, n, lds, "S"))) return rc;
+    if (n == 0) return PSVT_OK;
+    Layout L = make_layout(PSVT_OP_POLAR_SYM, n, n, c);
+    if ((rc = check_ws(ws, ws_bytes, L))) return rc;
+    if (overlaps(S, span_bytes(n, n, lds), G, span_bytes(n, n, ldg)) ||
+        overlaps(S, span_bytes(n, n, lds), ws, L.total) || overlaps(G, span_bytes(n, n, ldg), ws, L.total))
+        return fail(PSVT_EINVAL, "S, G and ws must not overlap");
+    if ((rc = check_device())) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    double *part = (double *)at(ws, L.part);
+    HIP_TRY(launch_fro_norm(G, n, n, ldg, part, sc, NORM_INPUT, 0.0, st), "norm of G");
+    HIP_TRY(launch_symmetrize_scale(G, n, ldg, F(ws, L.H), L.ldS, sc, st), "symmetrize");
+    HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, n, 1.0f, -1, 0.0f, -1, 0.0f, sc, st),
+            "G^2");
+    HIP_TRY(launch_fro_norm(F(ws, L.R), n, n, L.ldS, part, sc, NORM_THETA_S, 0.0, st), "theta_S");
+    return sign_iterations(c, L, ws, st, false, S, lds, nullptr);
+}
+
+int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const float *D, int64_t ldd, float *C,
+                 int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym, void *stream) {
+    g_last_error.clear();
+    if (M < 0 || N < 0 || K < 0) return fail(PSVT_EINVAL, "negative size");
+    if (M == 0 || N == 0) return PSVT_OK;
+    if (M > (1LL << 30) || N > (1LL << 30) || K > (1LL << 30)) return fail(PSVT_EINVAL, "size too large");
+    if (!C) return fail(PSVT_EINVAL, "C is NULL");
+    if (K > 0 && (!A || !B)) return fail(PSVT_EINVAL, "A or B is NULL");
+    if (ldc < N || (K > 0 && (lda < K || ldb < K)) || (D && ldd < N)) return fail(PSVT_EINVAL, "bad leading dimension");
+    if (sym && M != N) return fail(PSVT_EINVAL, "sym needs M == N");
+    auto al16 = [](const void *p, int64_t ld) { return p == nullptr || (((uintptr_t)p & 15) == 0 && ld % 4 == 0); };
+    if (!al16(A, lda) || !al16(B, ldb) || !al16(C, ldc) || !al16(D, ldd))
+        return fail(PSVT_EINVAL, "operands must be 16-byte aligned with ld a multiple of 4");
+    int rc = check_device();
+    if (rc) return rc;
+    GemmArgs g = gemm_defaults();
+    g.A = A;
+    g.B = B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.D = D;
+    g.ldd = ldd;
+    g.C = C;
+    g.ldc = ldc;
+    g.M = (int)M;
+    g.N = (int)N;
+    g.K = (int)K;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.sym = sym ? 1 : 0;
+    Scalars *none = nullptr;
+    g.sc = none;
+    HIP_TRY(launch_gemm(g, OP_F32, (hipStream_t)stream), "gemm");
+    return PSVT_OK;
+}
+
+const char *psvt_strerror(int code) {
+    switch (code) {
+        case PSVT_OK: return "success";
+        case PSVT_EINVAL: return "invalid argument";
+        case PSVT_EWORKSPACE: return "workspace missing or too small";
+        case PSVT_EUNSUPPORTED: return "unsupported device or option";
+        case PSVT_EHIP: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+const char *psvt_last_error(void) { return g_last_error.c_str(); }
+
+const char *psvt_version(void) { return "psvt 0.1 (gfx950)"; }
+
+}  // extern "C"

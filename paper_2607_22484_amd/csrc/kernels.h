@@ -1,0 +1,89 @@
+// Internal interface between the host planner (api.hip) and the gfx950
+// kernels (kernels.hip).  Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psvt {
+
+// Indices into the per-call device scalar block (float part).
+enum ScalarIdx {
+    F_INV_NU = 0,  // 1 / ||input||_F
+    F_NU = 1,      // ||input||_F
+    F_P1 = 2,      // 1 / theta_P, theta_P = sqrt(||X0^T X0||_F) >= sigma_max(X0)
+    F_P2 = 3,      // 1 / theta_P^2
+    F_P4 = 4,      // 1 / theta_P^4
+    F_S1 = 5,      // 1 / theta_S, theta_S = sqrt(||H^2||_F) >= |lambda|_max(H)
+    F_S2 = 6,
+    F_S4 = 7,
+    F_COUNT = 16
+};
+// double part
+enum DScalarIdx {
+    D_NU = 0,     // ||input||_F
+    D_SHIFT = 1,  // (tau / nu)^2: the Gram shift in the scaled problem
+    D_NORM = 2,   // last norm reduced
+    D_COUNT = 8
+};
+
+struct Scalars {
+    double d[D_COUNT];
+    float f[F_COUNT];
+};
+
+// Element types of the GEMM operands.
+enum OpType { OP_F32 = 0, OP_BF16 = 1, OP_FP8 = 2 };
+
+// One NT product with a fused prologue and epilogue:
+//   W[i][k]  = wa * A[i][k] (+ wa2 * A2[i][k])               (prologue)
+//   v[i][j]  = alpha * sum_k W[i][k] B[j][k] + beta * D[i][j] + diag*[i==j]
+//   C[i][j]  = v,  CT[j][i] = v                              (epilogue)
+// Every float multiplier is (host value) x (device scalar f[idx]) when
+// idx >= 0.  sym: M == N, only block tiles with bi >= bj run, and each
+// lower-triangle value is written to [i][j] and [j][i].
+struct GemmArgs {
+    const void *A;
+    const void *A2;
+    const void *B;
+    const float *D;
+    float *C;
+    float *CT;
+    void *Clp;   // optional low-precision row-major copy of v (type lp_type)
+    void *CTlp;  // optional low-precision transposed copy
+    int64_t lda, lda2, ldb, ldd, ldc, ldct, ldclp, ldctlp;
+    int M, N, K;
+    float alpha, beta, wa, wa2, diag;
+    float lp_scale;  // low-precision copies store v * lp_scale
+    float ab_scale;  // accumulator multiplier undoing operand scales (1 for f32)
+    int i_alpha, i_beta, i_wa, i_wa2;
+    const Scalars *sc;
+    int sym;
+    int c_vec;       // C may take 16-byte stores (aligned, ldc % 4 == 0)
+    int ct_vec;      // CT may take 16-byte stores
+    int lp_type;     // OpType of Clp/CTlp
+};
+
+// Launchers (enqueue only).  Return a hipError_t.
+hipError_t launch_gemm(const GemmArgs &g, int op_type, hipStream_t st);
+hipError_t launch_fro_norm(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials,
+                           Scalars *sc, int mode, double tau, hipStream_t st);
+hipError_t launch_scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda, float *Y, int64_t ldy,
+                                  float *YT, int64_t ldyt, const Scalars *sc, int i_scale, hipStream_t st);
+hipError_t launch_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc,
+                             hipStream_t st);
+hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, int64_t ldh,
+                                   const Scalars *sc, hipStream_t st);
+hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy,
+                          int op_type, float scale, int transpose, hipStream_t st);
+
+// modes for launch_fro_norm
+enum NormMode {
+    NORM_INPUT = 0,    // D_NU, D_SHIFT (needs tau), F_INV_NU, F_NU
+    NORM_THETA_P = 1,  // F_P1, F_P2, F_P4 from theta = sqrt(norm)
+    NORM_THETA_S = 2,  // F_S1, F_S2, F_S4
+    NORM_ONLY = 3      // D_NORM only
+};
+
+constexpr int NORM_PARTIALS = 1024;
+
+}  // namespace psvt

@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2607_22484_amd as psvt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "psvt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psvt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = psvt.load()
+    names = header_symbols()
+    assert names, "no declarations found"
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(psvt.EXPORTED) == names
+
+
+def test_strerror_and_version():
+    lib = psvt.load()
+    assert lib.psvt_strerror(0) == b"success"
+    assert lib.psvt_strerror(psvt.PSVT_EWORKSPACE).startswith(b"workspace")
+    assert b"gfx950" in lib.psvt_version()
+
+
+def test_workspace_bytes():
+    n1 = psvt.workspace_bytes(psvt.OP_SVT, 256, 128)
+    n2 = psvt.workspace_bytes(psvt.OP_SVT, 4096, 4096)
+    assert 0 < n1 < n2
+    assert psvt.workspace_bytes(psvt.OP_SVT, 0, 5) == 0
+    # left- and right-sided plans of transposed shapes need the same space
+    assert psvt.workspace_bytes(psvt.OP_SVT, 300, 200) == psvt.workspace_bytes(psvt.OP_SVT, 200, 300)
+    assert psvt.workspace_bytes(psvt.OP_RANK_R, 512, 512) < psvt.workspace_bytes(psvt.OP_SVT, 512, 512)
+    with pytest.raises(psvt.PsvtError):
+        psvt.workspace_bytes(psvt.OP_POLAR_SYM, 5, 6)
+    with pytest.raises(psvt.PsvtError):
+        psvt.workspace_bytes(9, 5, 6)
+
+
+FAKE = ctypes.c_void_p(1 << 40)  # never dereferenced: every call below fails validation first
+
+
+def call_svt(m=8, n=4, lda=4, tau=0.5, Y=FAKE, ldy=4, ws=FAKE, ws_bytes=1 << 30, cfg=None, A=FAKE):
+    lib = psvt.load()
+    return lib.psvt_svt(A, m, n, lda, tau, Y, ldy, ws, ws_bytes, ctypes.byref(cfg) if cfg else None, None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(lda=3), dict(ldy=2), dict(tau=-1.0), dict(tau=float("nan")), dict(tau=float("inf")),
+    dict(A=None), dict(Y=None), dict(m=-1),
+])
+def test_svt_rejects_bad_arguments(kw):
+    assert call_svt(**kw) == psvt.PSVT_EINVAL
+    assert psvt.load().psvt_last_error()
+
+
+def test_svt_workspace_errors():
+    assert call_svt(ws=None) == psvt.PSVT_EWORKSPACE
+    assert call_svt(ws_bytes=16) == psvt.PSVT_EWORKSPACE
+    assert call_svt(ws=ctypes.c_void_p((1 << 40) + 8)) == psvt.PSVT_EINVAL  # misaligned
+
+
+def test_svt_rejects_overlap():
+    # Y inside the workspace range
+    assert call_svt(Y=ctypes.c_void_p((1 << 40) + 4096)) == psvt.PSVT_EINVAL
+
+
+def test_config_validation():
+    cfg, _ = psvt.make_config(iters=300)
+    assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    cfg, _ = psvt.make_config(iters=4, n_bf16=3, n_fp8=2)
+    assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    cfg, _ = psvt.make_config(side=7)
+    assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    cfg, keep = psvt.make_config(iters=2, coeffs=[1.0, 0.0, float("nan"), 1, 0, 0])
+    assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+
+
+def test_empty_is_noop():
+    # m == 0 returns before any pointer is used
+    assert call_svt(m=0, A=None, Y=None, ws=None) == psvt.PSVT_OK
+
+
+def test_other_entry_points_validate():
+    lib = psvt.load()
+    assert lib.psvt_polar(FAKE, 5, 4, 3, FAKE, 4, FAKE, 1 << 30, None, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_polar_sym(FAKE, 5, 4, FAKE, 5, FAKE, 1 << 30, None, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_rank_r(FAKE, 5, 4, 4, -0.1, FAKE, 4, FAKE, 1 << 30, None, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_gemm_nt(FAKE, 4, FAKE, 4, None, 0, FAKE, 4, 3, 4, 4, 1.0, 0.0, 1, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_gemm_nt(ctypes.c_void_p((1 << 40) + 4), 4, FAKE, 4, None, 0, FAKE, 4, 4, 4, 4, 1.0, 0.0, 0,
+                            None) == psvt.PSVT_EINVAL
+
+
+def test_python_wrapper_rejects_non_2d():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        psvt.svt(torch.zeros(2, 3, 4), 0.1)
+    with pytest.raises(TypeError):
+        psvt.svt(torch.zeros(3, 4, dtype=torch.float64), 0.1)
+    with pytest.raises(TypeError):
+        psvt.svt(torch.zeros(3, 4), 0.1)  # CPU tensor
