@@ -1,0 +1,199 @@
+#!/usr/bin/env python
+"""Throughput of singular value soft-thresholding through the polar
+decomposition on one MI355X.
+
+Workload (one step): the plain FP32 form on three 4096 x 4096 matrices
+A = U diag(sigma) V^T (Haar U, V; sigma log-spaced 10 .. 1e-3), one per
+threshold tau at the 10 / 50 / 90 % quantile of sigma (each gap-clamped so
+every singular value sits >= 5 % from tau), 20 polar iterations, one matrix
+per launch sequence.  Inputs, outputs and workspace are resident in HBM
+before the timed region.
+
+Printed: one JSON line with matrices/s, useful TFLOP/s and MFMA utilisation
+against the FP32 MFMA peak, per-matrix latency p50/p99, the dominant
+kernel's roofline (timed per launch with HIP events on its own stream
+through the library's trace facility), and the FP64 CPU oracle timed on a
+bounded sample on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2516.6, "fp8": 5033.2}
+HBM_GBS = 8000.0
+METRIC = "SVT matrices/s + MFMA util (bf16 vs fp32) at rel err≤1e-2; p50/p99 latency"
+
+
+def useful_flops(m, n, iters, with_p=True):
+    """Flops the method must perform for one SVT (symmetric products at half):
+    K (3 l s^2 + s^3) for P, l s^2 for the Gram, 3 K s^3 for S, 2 l s^2 for the
+    final product."""
+    s, l = min(m, n), max(m, n)
+    f = l * s * s + 3 * iters * s ** 3 + 2 * l * s * s
+    if with_p:
+        f += iters * (3 * l * s * s + s ** 3)
+    return float(f)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline_leg(problems, results, n_sample):
+    """FP64 Jacobi oracle timed on a bounded sample, plus the accuracy of the
+    GPU results against the oracle (constructed factors: Eq. (1) exactly)."""
+    import oracle
+    from paper_2607_22484_amd import inputs
+
+    errs = {}
+    for pb, Y in zip(problems, results):
+        ref = oracle.svt_from_svd(pb.U, pb.sigma, pb.V, pb.tau)
+        nref = np.linalg.norm(ref)
+        err = np.linalg.norm(Y - ref)
+        delta = float(np.linalg.norm(pb.A.astype(np.float64) - pb.A64))  # prox is 1-Lipschitz
+        errs[pb.name] = {"rel_err": float(err / nref), "rel_err_bound_fp32_input": float((err + delta) / (nref - delta))}
+    sample = inputs.square_case(0.5, n=n_sample)
+    t0 = time.perf_counter()
+    oracle.svt(sample.A, sample.tau)
+    dt = time.perf_counter() - t0
+    scale = (problems[0].A.shape[0] / n_sample) ** 3
+    cpu = {
+        "value": 1.0 / (dt * scale),
+        "unit": "matrices/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": "one-sided Jacobi SVD + threshold (FP64, OpenMP) of one %dx%d matrix of the same recipe "
+                  "(tau at the 50%% quantile) in %.2f s, scaled by (4096/%d)^3 = %.0f to one 4096x4096 matrix"
+                  % (n_sample, n_sample, dt, n_sample, scale),
+    }
+    return cpu, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (matrices are independent; "
+              "see the sharding note in the design document). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2607_22484_amd as psvt
+    from paper_2607_22484_amd import inputs
+
+    psvt.load()
+    dev = torch.device("cuda:0")
+    n = args.n
+    quantiles = (0.1, 0.5, 0.9)
+    t_gen = time.perf_counter()
+    problems = [inputs.square_case(q, n=n) for q in quantiles]
+    print("[bench] inputs generated in %.1f s" % (time.perf_counter() - t_gen), file=sys.stderr, flush=True)
+    A = [torch.from_numpy(pb.A).to(dev) for pb in problems]
+    Y = [torch.empty_like(a) for a in A]
+    cfg, _ = psvt.make_config(iters=args.iters)
+    ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, n, n, cfg), dtype=torch.uint8, device=dev)
+    taus = [pb.tau for pb in problems]
+    stream = torch.cuda.current_stream(dev)
+
+    def step(lat=None):
+        for a, y, tau in zip(A, Y, taus):
+            if lat is not None:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            psvt.svt(a, tau, iters=args.iters, out=y, ws=ws)
+            if lat is not None:
+                e1.record(stream)
+                lat.append((e0, e1))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    lat = []
+    psvt.trace_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(lat)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    trace = psvt.trace_end()
+    lat_ms = [e0.elapsed_time(e1) for e0, e1 in lat]
+    print("[bench] timed %d steps in %.3f s" % (args.steps, elapsed), file=sys.stderr, flush=True)
+
+    n_mat = len(A) * args.steps
+    ms_per_step = 1e3 * elapsed / args.steps
+    flops_step = sum(useful_flops(n, n, args.iters) for _ in A)
+    tflops = flops_step / (ms_per_step * 1e-3) / 1e12
+
+    products = [t for t in trace if t["flops"] > 0]
+    dom = max(products, key=lambda t: t["total_ms"])
+    dom_avg_ms = dom["total_ms"] / dom["launches"]
+    dom_tflops = dom["flops"] / (dom["total_ms"] * 1e-3) / 1e12
+    roofline = {
+        "bound": "mfma", "kernel": dom["name"], "launches": dom["launches"], "avg_launch_ms": dom_avg_ms,
+        "flops_per_launch": dom["flops"] / dom["launches"],
+        "achieved": dom_tflops, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+        "frac": dom_tflops / PEAK_TFLOPS["f32"], "traffic": None,
+    }
+    kernels = [{"name": t["name"], "launches": t["launches"], "ms_per_step": t["total_ms"] / args.steps,
+                "tflops": (t["flops"] / (t["total_ms"] * 1e-3) / 1e12) if t["flops"] else None,
+                "gbs": (t["bytes"] / (t["total_ms"] * 1e-3) / 1e9) if t["bytes"] else None} for t in trace]
+
+    out = {
+        "metric": METRIC,
+        "value": n_mat / elapsed,
+        "unit": "matrices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain FP32 SVT, %dx%d, %d polar iterations, tau at the 10/50/90%% quantiles of a "
+                        "log-spaced spectrum 10..1e-3 (gap-clamped), 3 matrices per step, one per launch sequence"
+                        % (n, n, args.iters),
+            "m": n, "n": n, "iters": args.iters, "matrices_per_step": len(A), "side": "left (square)",
+        },
+        "useful_tflops": tflops,
+        "mfma_util": tflops / PEAK_TFLOPS["f32"],
+        "latency_ms": {"p50": percentile(lat_ms, 0.5), "p99": percentile(lat_ms, 0.99)},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    if not args.no_cpu:
+        res = [y.cpu().numpy().astype(np.float64) for y in Y]
+        print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
+        cpu, errs = cpu_baseline_leg(problems, res, args.cpu_sample)
+        out["cpu_baseline"] = cpu
+        out["accuracy"] = errs
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

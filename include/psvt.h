@@ -116,6 +116,26 @@ int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, f
 int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const float *D, int64_t ldd, float *C,
                  int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym, void *stream);
 
+/* Launch tracing.  psvt_trace_begin() starts recording every kernel launch
+ * that the library makes from the calling thread: each is bracketed by two
+ * HIP events recorded on the launch's stream (so the elapsed time is device
+ * time of that launch alone).  psvt_trace_end() waits for the recorded
+ * events (a host synchronisation), aggregates them per kernel name, most
+ * time first, writes up to max_entries rows to `out` and stops recording.
+ * `flops` are useful flops (a symmetric product counts half), `bytes` the
+ * algorithmic HBM bytes of memory-bound kernels (0 for products).  Names are
+ * static strings.  Meant for profiling: the events add a few microseconds
+ * per launch. */
+typedef struct psvt_trace_stat {
+    const char *name;
+    int64_t launches;
+    double total_ms;
+    double flops;
+    double bytes;
+} psvt_trace_stat;
+int psvt_trace_begin(void);
+int psvt_trace_end(psvt_trace_stat *out, int max_entries, int *n_entries);
+
 /* Static description of a return code. */
 const char *psvt_strerror(int code);
 

@@ -28,7 +28,7 @@ SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 
 EXPORTED = [
     "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt",
-    "psvt_strerror", "psvt_last_error", "psvt_version",
+    "psvt_strerror", "psvt_last_error", "psvt_version", "psvt_trace_begin", "psvt_trace_end",
 ]
 
 
@@ -49,6 +49,12 @@ class Config(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("reserved", ctypes.c_int32 * 3),
     ]
+
+
+class TraceStat(ctypes.Structure):
+    """Mirror of ``psvt_trace_stat``."""
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -78,6 +84,9 @@ def load(path: Optional[str] = None):
     lib.psvt_strerror.restype = ctypes.c_char_p
     lib.psvt_last_error.restype = ctypes.c_char_p
     lib.psvt_version.restype = ctypes.c_char_p
+    lib.psvt_trace_begin.restype = ctypes.c_int
+    lib.psvt_trace_end.restype = ctypes.c_int
+    lib.psvt_trace_end.argtypes = [ctypes.POINTER(TraceStat), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     _lib = lib
     return lib
 
@@ -241,6 +250,20 @@ def gemm_nt(A, B, D=None, alpha: float = 1.0, beta: float = 0.0, sym: bool = Fal
                                    M, N, K, float(alpha), float(beta), 1 if sym else 0, _stream_ptr(A)),
                "psvt_gemm_nt")
     return C
+
+
+def trace_begin():
+    """Start per-launch event tracing on this thread."""
+    _check(load().psvt_trace_begin(), "psvt_trace_begin")
+
+
+def trace_end(max_entries: int = 64):
+    """Stop tracing; returns [{name, launches, total_ms, flops, bytes}] by time."""
+    rows = (TraceStat * max_entries)()
+    n = ctypes.c_int(0)
+    _check(load().psvt_trace_end(rows, max_entries, ctypes.byref(n)), "psvt_trace_end")
+    return [dict(name=r.name.decode(), launches=int(r.launches), total_ms=float(r.total_ms), flops=float(r.flops),
+                 bytes=float(r.bytes)) for r in rows[:n.value]]
 
 
 def version() -> str:

@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "kernels.h"
+#include "trace.h"
 
 namespace psvt {
 
@@ -70,7 +71,7 @@ __device__ __forceinline__ void grouped_index(int t, int nbm, int nbn, int &bi, 
 
 // BM x BN block tile, 256 threads = 2 x 2 waves, each wave (BM/2) x (BN/2)
 // made of TM x TN 32x32 MFMA blocks.  BK = 32 floats.
-template <int BM, int BN, bool TWO_A>
+template <int BM, int BN, bool TWO_A, bool SYM>
 __global__ __launch_bounds__(256, 2) void gemm_nt_f32(GemmArgs g) {
     constexpr int BK = 32;
     constexpr int LDS = BK + 4;  // row stride in floats (144 bytes)
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f32(GemmArgs g) {
     int bi, bj;
     {
         const int t = xcd_remap(blockIdx.x, gridDim.x);
-        if (g.sym)
+        if (SYM)
             tri_index(t, bi, bj);
         else
             grouped_index<8>(t, nbm, nbn, bi, bj);
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f32(GemmArgs g) {
     // ------------------------------------------------------------ epilogue
     const float alpha = g.alpha * scal(g.sc, g.i_alpha) * g.ab_scale;
     const float beta = g.D ? g.beta * scal(g.sc, g.i_beta) : 0.0f;
-    const bool diag_tile = g.sym && (bi == bj);
+    const bool diag_tile = SYM && (bi == bj);
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
 #pragma unroll
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f32(GemmArgs g) {
                     v[e] = x;
                 }
                 if (j >= g.N) continue;
-                if (!g.sym) {
+                if (!SYM) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         if (ib + e < g.M && g.C) g.C[(int64_t)(ib + e) * g.ldc + j] = v[e];
@@ -244,10 +245,18 @@ static hipError_t launch_f32(const GemmArgs &g, hipStream_t st) {
     const int nbm = (g.M + BM - 1) / BM, nbn = (g.N + BN - 1) / BN;
     const int nblocks = g.sym ? nbm * (nbm + 1) / 2 : nbm * nbn;
     if (nblocks == 0) return hipSuccess;
-    if (g.A2)
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, true>), dim3(nblocks), dim3(256), 0, st, g);
+    // useful flops: a symmetric product counts its lower triangle only
+    const double flops = g.sym ? (double)g.M * (g.M + 1) * g.K : 2.0 * g.M * g.N * g.K;
+    const char *name = g.sym ? (BM == 128 ? "syrk_f32_128" : "syrk_f32_64")
+                             : (g.A2 ? (BM == 128 ? "gemm2_f32_128" : "gemm2_f32_64")
+                                     : (BM == 128 ? "gemm_f32_128" : "gemm_f32_64"));
+    TraceScope tr(st, name, flops, 0.0);
+    if (g.sym)
+        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, false, true>), dim3(nblocks), dim3(256), 0, st, g);
+    else if (g.A2)
+        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, true, false>), dim3(nblocks), dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, false>), dim3(nblocks), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, false, false>), dim3(nblocks), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
@@ -323,6 +332,7 @@ hipError_t launch_fro_norm(const float *X, int64_t rows, int64_t cols, int64_t l
                            Scalars *sc, int mode, double tau, hipStream_t st) {
     int nb = (int)(rows < NORM_PARTIALS ? rows : NORM_PARTIALS);
     if (nb < 1) nb = 1;
+    TraceScope tr(st, "fro_norm", 0.0, 4.0 * rows * cols);
     hipLaunchKernelGGL(fro_partial, dim3(nb), dim3(256), 0, st, X, rows, cols, ld, partials);
     hipLaunchKernelGGL(fro_final, dim3(1), dim3(256), 0, st, partials, nb, sc, mode, tau);
     return hipGetLastError();
@@ -360,6 +370,7 @@ hipError_t launch_scale_transpose(const float *A, int64_t m, int64_t n, int64_t 
                                   float *YT, int64_t ldyt, const Scalars *sc, int i_scale, hipStream_t st) {
     if (m <= 0 || n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
+    TraceScope tr(st, "scale_transpose", 0.0, 4.0 * m * n * (1 + (Y != nullptr) + (YT != nullptr)));
     hipLaunchKernelGGL(scale_transpose, grid, dim3(256), 0, st, A, m, n, lda, Y, ldy, YT, ldyt, sc, i_scale);
     return hipGetLastError();
 }
@@ -384,6 +395,7 @@ hipError_t launch_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, i
                              hipStream_t st) {
     if (s <= 0) return hipSuccess;
     const int nb = (int)(s < 2048 ? s : 2048);
+    TraceScope tr(st, "shift_copy", 0.0, 8.0 * s * s);
     hipLaunchKernelGGL(shift_copy, dim3(nb), dim3(256), 0, st, T, s, ldt, H, ldh, sc);
     return hipGetLastError();
 }
@@ -411,6 +423,7 @@ hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float
                                    const Scalars *sc, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
+    TraceScope tr(st, "symmetrize_scale", 0.0, 12.0 * n * n);
     hipLaunchKernelGGL(symmetrize_scale, grid, dim3(256), 0, st, G, n, ldg, H, ldh, sc);
     return hipGetLastError();
 }
