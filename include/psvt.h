@@ -136,6 +136,27 @@ typedef struct psvt_trace_stat {
 int psvt_trace_begin(void);
 int psvt_trace_end(psvt_trace_stat *out, int max_entries, int *n_entries);
 
+/* Tile configurations of the MFMA kernels.  Ids: 1 = 64x64 tiles (4 blocks
+ * per CU), 2 = 128x128 (2 per CU), 3 = 192x192 (1 per CU), 4 = 256x256
+ * (1 per CU).  Each product picks the configuration with the smallest
+ * modelled time
+ *     (most tiles on one CU) x (overhead + tile flops / (eff x CU rate)),
+ * with (eff, overhead) per configuration and per kind (sym = 1 for the
+ * lower-triangle products, 0 for full ones) measured by the autotuner.
+ *   psvt_tune_force_tile(id)   force a configuration on the calling thread
+ *                              (0 = automatic).
+ *   psvt_tune_set(id, sym, eff, overhead_us)   eff in (0, 1], overhead >= 0.
+ *   psvt_tune_load(path)       read "id sym eff overhead_us" lines ('#'
+ *                              starts a comment); PSVT_EINVAL on a malformed
+ *                              line, and then nothing is applied.
+ *   psvt_tune_pick             the id the model picks for an M x N x K
+ *                              product (>= 1), or a negative error code.
+ * The model is process-wide; change it before concurrent calls. */
+int psvt_tune_force_tile(int tile);
+int psvt_tune_set(int tile, int sym, double efficiency, double overhead_us);
+int psvt_tune_load(const char *path);
+int psvt_tune_pick(int64_t M, int64_t N, int64_t K, int sym);
+
 /* Static description of a return code. */
 const char *psvt_strerror(int code);
 

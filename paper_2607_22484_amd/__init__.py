@@ -29,7 +29,10 @@ SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 EXPORTED = [
     "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt",
     "psvt_strerror", "psvt_last_error", "psvt_version", "psvt_trace_begin", "psvt_trace_end",
+    "psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick",
 ]
+TILE_IDS = {64: 1, 128: 2, 192: 3, 256: 4}
+TUNE_TABLE = os.path.join(_HERE, "tune_table.txt")
 
 
 class PsvtError(RuntimeError):
@@ -84,9 +87,19 @@ def load(path: Optional[str] = None):
     lib.psvt_strerror.restype = ctypes.c_char_p
     lib.psvt_last_error.restype = ctypes.c_char_p
     lib.psvt_version.restype = ctypes.c_char_p
+    lib.psvt_tune_force_tile.argtypes = [ctypes.c_int]
+    lib.psvt_tune_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    lib.psvt_tune_load.argtypes = [ctypes.c_char_p]
+    lib.psvt_tune_pick.argtypes = [i64, i64, i64, ctypes.c_int]
+    for f in ("psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick"):
+        getattr(lib, f).restype = ctypes.c_int
     lib.psvt_trace_begin.restype = ctypes.c_int
     lib.psvt_trace_end.restype = ctypes.c_int
     lib.psvt_trace_end.argtypes = [ctypes.POINTER(TraceStat), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    if os.path.exists(TUNE_TABLE):
+        rc = lib.psvt_tune_load(TUNE_TABLE.encode())
+        if rc != PSVT_OK:
+            raise PsvtError(rc, "psvt_tune_load", lib.psvt_last_error().decode())
     _lib = lib
     return lib
 
@@ -264,6 +277,18 @@ def trace_end(max_entries: int = 64):
     _check(load().psvt_trace_end(rows, max_entries, ctypes.byref(n)), "psvt_trace_end")
     return [dict(name=r.name.decode(), launches=int(r.launches), total_ms=float(r.total_ms), flops=float(r.flops),
                  bytes=float(r.bytes)) for r in rows[:n.value]]
+
+
+def force_tile(tile: int):
+    """Force a tile configuration id (0 = automatic) on this thread."""
+    _check(load().psvt_tune_force_tile(int(tile)), "psvt_tune_force_tile")
+
+
+def pick_tile(M: int, N: int, K: int, sym: bool = False) -> int:
+    rc = load().psvt_tune_pick(M, N, K, 1 if sym else 0)
+    if rc < 0:
+        _check(rc, "psvt_tune_pick")
+    return rc
 
 
 def version() -> str:

@@ -584,6 +584,54 @@ int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const
     return PSVT_OK;
 }
 
+int psvt_tune_force_tile(int tile) {
+    if (tile < 0 || tile > 4) return fail(PSVT_EINVAL, "tile id %d outside 0..4", tile);
+    tune_force_tile(tile);
+    return PSVT_OK;
+}
+
+int psvt_tune_set(int tile, int sym, double efficiency, double overhead_us) {
+    if (tune_set_model(tile, sym, (float)efficiency, (float)overhead_us) != 0)
+        return fail(PSVT_EINVAL, "bad tuning entry %d %d %g %g", tile, sym, efficiency, overhead_us);
+    return PSVT_OK;
+}
+
+int psvt_tune_load(const char *path) {
+    if (!path) return fail(PSVT_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(PSVT_EINVAL, "cannot open %s", path);
+    struct Entry {
+        int id, sym;
+        double e, o;
+    } ent[32];
+    char line[256];
+    int n = 0, lineno = 0;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        char *hash = strchr(line, '#');
+        if (hash) *hash = 0;
+        Entry e;
+        char extra[8];
+        const int got = sscanf(line, "%d %d %lf %lf %7s", &e.id, &e.sym, &e.e, &e.o, extra);
+        if (got <= 0) continue;  // blank or comment
+        if (got != 4 || e.id < 1 || e.id > 4 || (e.sym != 0 && e.sym != 1) || !(e.e > 0.0 && e.e <= 1.0) ||
+            !(e.o >= 0.0 && e.o < 1e6) || n >= 32) {
+            fclose(f);
+            return fail(PSVT_EINVAL, "%s:%d: expected 'id sym efficiency overhead_us'", path, lineno);
+        }
+        ent[n++] = e;
+    }
+    fclose(f);
+    for (int i = 0; i < n; ++i) tune_set_model(ent[i].id, ent[i].sym, (float)ent[i].e, (float)ent[i].o);
+    return PSVT_OK;
+}
+
+int psvt_tune_pick(int64_t M, int64_t N, int64_t K, int sym) {
+    if (M <= 0 || N <= 0 || K < 0 || M > (1LL << 30) || N > (1LL << 30) || K > (1LL << 30))
+        return fail(PSVT_EINVAL, "bad size");
+    return tune_pick((int)M, (int)N, (int)K, sym ? 1 : 0);
+}
+
 const char *psvt_strerror(int code) {
     switch (code) {
         case PSVT_OK: return "success";

@@ -86,4 +86,9 @@ enum NormMode {
 
 constexpr int NORM_PARTIALS = 1024;
 
+// Tile-configuration control (autotuner and tests).
+void tune_force_tile(int c);
+int tune_set_model(int c, int sym, float e, float overhead_us);
+int tune_pick(int M, int N, int K, int sym);
+
 }  // namespace psvt

@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <string.h>
 
 #include "kernels.h"
 #include "trace.h"
@@ -71,8 +73,8 @@ __device__ __forceinline__ void grouped_index(int t, int nbm, int nbn, int &bi, 
 
 // BM x BN block tile, 256 threads = 2 x 2 waves, each wave (BM/2) x (BN/2)
 // made of TM x TN 32x32 MFMA blocks.  BK = 32 floats.
-template <int BM, int BN, bool TWO_A, bool SYM>
-__global__ __launch_bounds__(256, 2) void gemm_nt_f32(GemmArgs g) {
+template <int BM, int BN, int OCC, bool TWO_A, bool SYM>
+__global__ __launch_bounds__(256, OCC) void gemm_nt_f32(GemmArgs g) {
     constexpr int BK = 32;
     constexpr int LDS = BK + 4;  // row stride in floats (144 bytes)
     constexpr int TM = BM / 64, TN = BN / 64;
@@ -240,23 +242,71 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f32(GemmArgs g) {
     }
 }
 
-template <int BM, int BN>
-static hipError_t launch_f32(const GemmArgs &g, hipStream_t st) {
-    const int nbm = (g.M + BM - 1) / BM, nbn = (g.N + BN - 1) / BN;
-    const int nblocks = g.sym ? nbm * (nbm + 1) / 2 : nbm * nbn;
+// Tile configurations of the FP32 kernel: block tile, blocks per CU.
+struct TileCfg {
+    int bm, occ;
+    const char *tag;
+};
+static const TileCfg kTiles[] = {{0, 0, ""}, {64, 4, "64"}, {128, 2, "128"}, {192, 1, "192"}, {256, 1, "256"}};
+constexpr int kNumTiles = 4;
+
+// Cost model of one product in configuration c (sym = lower-triangle
+// product or full one):  time ~= (most tiles on one CU) x (overhead +
+// tile flops / (efficiency x CU FP32 MFMA rate)).  The efficiency and the
+// per-tile overhead (prologue/epilogue, in microseconds) come from the
+// autotuner's table (psvt_tune_set / psvt_tune_load); these defaults are a
+// measured starting point.
+struct TileModel {
+    float eff, overhead_us;
+};
+static TileModel g_model[2][kNumTiles + 1] = {
+    {{0.f, 0.f}, {0.60f, 4.0f}, {0.72f, 6.0f}, {0.71f, 8.0f}, {0.77f, 10.0f}},
+    {{0.f, 0.f}, {0.60f, 4.0f}, {0.70f, 6.0f}, {0.71f, 8.0f}, {0.45f, 10.0f}},
+};
+static thread_local int g_force_tile = 0;
+constexpr double kCuRate = 157.3e12 / 256.0;  // FP32 MFMA flop/s of one CU
+
+int tile_count(const GemmArgs &g, int bm) {
+    const int nbm = (g.M + bm - 1) / bm, nbn = (g.N + bm - 1) / bm;
+    return g.sym ? nbm * (nbm + 1) / 2 : nbm * nbn;
+}
+
+double model_time_us(const GemmArgs &g, int c) {
+    const double bm = kTiles[c].bm;
+    const double per_cu = ceil(tile_count(g, kTiles[c].bm) / 256.0);
+    const TileModel &tm = g_model[g.sym ? 1 : 0][c];
+    return per_cu * (tm.overhead_us + 1e6 * bm * bm * 2.0 * g.K / (tm.eff * kCuRate));
+}
+
+int pick_tile(const GemmArgs &g) {
+    if (g_force_tile >= 1 && g_force_tile <= kNumTiles) return g_force_tile;
+    double best = 1e300;
+    int arg = 2;
+    for (int c = 1; c <= kNumTiles; ++c) {
+        const double t = model_time_us(g, c);
+        if (t < best * 0.999) {
+            best = t;
+            arg = c;
+        }
+    }
+    return arg;
+}
+
+template <int BM, int OCC>
+static hipError_t launch_f32(const GemmArgs &g, hipStream_t st, const char *tag) {
+    const int nblocks = tile_count(g, BM);
     if (nblocks == 0) return hipSuccess;
     // useful flops: a symmetric product counts its lower triangle only
     const double flops = g.sym ? (double)g.M * (g.M + 1) * g.K : 2.0 * g.M * g.N * g.K;
-    const char *name = g.sym ? (BM == 128 ? "syrk_f32_128" : "syrk_f32_64")
-                             : (g.A2 ? (BM == 128 ? "gemm2_f32_128" : "gemm2_f32_64")
-                                     : (BM == 128 ? "gemm_f32_128" : "gemm_f32_64"));
-    TraceScope tr(st, name, flops, 0.0);
+    char name[32];
+    snprintf(name, sizeof name, "%s_f32_%s", g.sym ? "syrk" : (g.A2 ? "gemm2" : "gemm"), tag);
+    TraceScope tr(st, trace_name(name), flops, 0.0);
     if (g.sym)
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, false, true>), dim3(nblocks), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_nt_f32<BM, BM, OCC, false, true>), dim3(nblocks), dim3(256), 0, st, g);
     else if (g.A2)
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, true, false>), dim3(nblocks), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_nt_f32<BM, BM, OCC, true, false>), dim3(nblocks), dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BN, false, false>), dim3(nblocks), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_nt_f32<BM, BM, OCC, false, false>), dim3(nblocks), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
@@ -266,10 +316,30 @@ hipError_t launch_gemm(const GemmArgs &g_in, int op_type, hipStream_t st) {
     g.c_vec = g.C && ((uintptr_t)g.C & 15) == 0 && g.ldc % 4 == 0;
     g.ct_vec = g.CT && ((uintptr_t)g.CT & 15) == 0 && g.ldct % 4 == 0;
     if (op_type != OP_F32) return hipErrorInvalidValue;
-    // Small problems: 64x64 tiles give 4x more blocks to fill 256 CUs.
-    const int64_t tiles128 = ((int64_t)(g.M + 127) / 128) * ((g.N + 127) / 128);
-    if (tiles128 < 512) return launch_f32<64, 64>(g, st);
-    return launch_f32<128, 128>(g, st);
+    switch (pick_tile(g)) {
+        case 1: return launch_f32<64, 4>(g, st, "64");
+        case 3: return launch_f32<192, 1>(g, st, "192");
+        case 4: return launch_f32<256, 1>(g, st, "256");
+        default: return launch_f32<128, 2>(g, st, "128");
+    }
+}
+
+void tune_force_tile(int c) { g_force_tile = c; }
+int tune_set_model(int c, int sym, float e, float overhead_us) {
+    if (c < 1 || c > kNumTiles || (sym != 0 && sym != 1) || !(e > 0.0f && e <= 1.0f) ||
+        !(overhead_us >= 0.0f && overhead_us < 1e6f))
+        return -1;
+    g_model[sym][c] = TileModel{e, overhead_us};
+    return 0;
+}
+int tune_pick(int M, int N, int K, int sym) {
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.sym = sym;
+    return pick_tile(g);
 }
 
 // ---------------------------------------------------------------- norms

@@ -8,6 +8,9 @@ namespace psvt {
 
 bool trace_on();
 
+// Interned copy of `name` that lives until the process ends.
+const char *trace_name(const char *name);
+
 class TraceScope {
   public:
     TraceScope(hipStream_t st, const char *name, double flops, double bytes);

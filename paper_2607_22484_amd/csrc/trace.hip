@@ -3,6 +3,9 @@
 
 #include <string.h>
 
+#include <mutex>
+#include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/psvt.h"
@@ -37,6 +40,13 @@ thread_local State g_state;
 }  // namespace
 
 bool trace_on() { return g_state.on; }
+
+const char *trace_name(const char *name) {
+    static std::mutex mu;
+    static std::unordered_set<std::string> *names = new std::unordered_set<std::string>();
+    std::lock_guard<std::mutex> lock(mu);
+    return names->insert(name).first->c_str();
+}
 
 TraceScope::TraceScope(hipStream_t st, const char *name, double flops, double bytes)
     : st_(st), name_(name), flops_(flops), bytes_(bytes) {

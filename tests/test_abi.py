@@ -109,3 +109,32 @@ def test_python_wrapper_rejects_non_2d():
         psvt.svt(torch.zeros(3, 4, dtype=torch.float64), 0.1)
     with pytest.raises(TypeError):
         psvt.svt(torch.zeros(3, 4), 0.1)  # CPU tensor
+
+
+def test_tune_table_parsing(tmp_path):
+    lib = psvt.load()
+    good = tmp_path / "good.txt"
+    good.write_text("# comment\n1 0 0.5 10\n\n3 1 0.7 5.5  # trailing\n")
+    assert lib.psvt_tune_load(str(good).encode()) == psvt.PSVT_OK
+    for text in ["1 0 0.5\n", "5 0 0.5 1\n", "1 2 0.5 1\n", "1 0 1.5 1\n", "1 0 0.5 -1\n", "1 0 0.5 1 extra\n"]:
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        assert lib.psvt_tune_load(str(bad).encode()) == psvt.PSVT_EINVAL, text
+    assert lib.psvt_tune_load(str(tmp_path / "missing.txt").encode()) == psvt.PSVT_EINVAL
+    # restore the shipped table
+    if os.path.exists(psvt.TUNE_TABLE):
+        assert lib.psvt_tune_load(psvt.TUNE_TABLE.encode()) == psvt.PSVT_OK
+
+
+def test_tune_pick_model():
+    """The cost model: a full 4096 product fits one round of 256x256 tiles;
+    a symmetric 4096 product (lower triangle) fits one round of 192 tiles;
+    small products use the 64 tiles (more blocks)."""
+    lib = psvt.load()
+    assert lib.psvt_tune_load(psvt.TUNE_TABLE.encode()) == psvt.PSVT_OK
+    assert psvt.pick_tile(4096, 4096, 4096, True) == psvt.TILE_IDS[192]
+    assert psvt.pick_tile(4096, 4096, 4096, False) == psvt.TILE_IDS[256]
+    assert psvt.pick_tile(512, 512, 512, True) == psvt.TILE_IDS[64]
+    assert lib.psvt_tune_pick(0, 5, 5, 0) == psvt.PSVT_EINVAL
+    assert lib.psvt_tune_force_tile(9) == psvt.PSVT_EINVAL
+    assert lib.psvt_tune_set(1, 0, 0.0, 1.0) == psvt.PSVT_EINVAL

@@ -272,3 +272,47 @@ def test_square_4096_rank256(gpu_lib, torch_dev):
     rel = (err + delta * (1 + 2 * pb.sigma[0] / gap)) / nref
     print("rank256 rel err %.3e (with rounding allowance %.3e)" % (err / nref, rel))
     assert rel <= TOL_PLAIN
+
+
+# ------------------------------------------------ every tile configuration
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("M,N,K,sym", [(200, 328, 132, False), (450, 450, 300, True), (513, 260, 68, False)])
+def test_gemm_every_tile(gpu_lib, torch_dev, tile, M, N, K, sym):
+    torch, dev = torch_dev
+    _announce("gemm tile=%d %dx%dx%d sym=%s" % (tile, M, N, K, sym))
+    rng = np.random.default_rng([M, N, K, tile])
+    A = rng.standard_normal((M, K)).astype(np.float32)
+    B = A if sym else rng.standard_normal((N, K)).astype(np.float32)
+    gpu_lib.force_tile(tile)
+    try:
+        Ad = to_dev(torch, dev, A)
+        C = gpu_lib.gemm_nt(Ad, Ad if sym else to_dev(torch, dev, B), sym=sym,
+                            out=padded(torch, dev, np.zeros((M, N))))
+        got = to_np(C)
+    finally:
+        gpu_lib.force_tile(0)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    ref = A64 @ B64.T
+    bound = (np.abs(A64) @ np.abs(B64).T) * (K + 2) * 2.0 ** -24
+    assert np.all(np.abs(got - ref) <= bound + 1e-30)
+    if sym:
+        assert np.array_equal(got, got.T)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+def test_svt_every_tile(gpu_lib, torch_dev, tile):
+    """Whole method under each forced configuration (covers the transposed
+    writes, the two-operand prologue and the diagonal epilogue)."""
+    torch, dev = torch_dev
+    pb = inputs.square_case(0.4, n=200, m=300)
+    _announce("svt tile=%d" % tile)
+    gpu_lib.force_tile(tile)
+    try:
+        Y = to_np(gpu_lib.svt(to_dev(torch, dev, pb.A), pb.tau))
+        Yw = to_np(gpu_lib.svt(to_dev(torch, dev, pb.A.T.copy()), pb.tau))
+    finally:
+        gpu_lib.force_tile(0)
+    ref = oracle.svt(pb.A, pb.tau)
+    assert oracle.rel_fro_err(Y, ref) <= TOL_PLAIN
+    assert oracle.rel_fro_err(Yw, ref.T) <= TOL_PLAIN
