@@ -107,14 +107,28 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
 int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy, void *ws,
                 size_t ws_bytes, const psvt_config *cfg, void *stream);
 
-/* Building block exposed for kernel-level tests: the FP32 MFMA product
+/* Building blocks exposed for kernel-level tests and tuning.
+ *
+ * psvt_gemm_nt: the MFMA product used by every step of the method,
  *     C[i][j] = alpha * sum_k A[i][k] B[j][k] + beta * D[i][j]
- * (A: M x K, B: N x K, C, D: M x N; all row-major, device, ld multiple of 4,
- * 16-byte aligned).  D may be NULL (beta ignored).  sym != 0 requires M == N
- * and computes only the lower block triangle, mirroring it into the upper
- * one (valid when the product is symmetric, e.g. A = B). */
-int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const float *D, int64_t ldd, float *C,
-                 int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym, void *stream);
+ * with A (M x K) and B (N x K) stored in `dtype` (PSVT_DTYPE_F32: float,
+ * PSVT_DTYPE_BF16: bfloat16 bits, PSVT_DTYPE_FP8: OCP e4m3 bytes) and C, D
+ * (M x N) float32; all row-major device buffers, 16-byte aligned, with every
+ * row stride a multiple of 16 bytes.  Products accumulate in FP32.  D may be
+ * NULL.  sym != 0 requires M == N and computes only the lower block
+ * triangle, mirroring it into the upper one (valid when the product is
+ * symmetric, e.g. A = B).
+ *
+ * psvt_convert: Y = round(scale * X) into `dtype` (bfloat16: round to
+ * nearest even; FP8 e4m3: round to nearest even, saturated to +-448), or
+ * into float32 when dtype is PSVT_DTYPE_F32; transpose != 0 writes
+ * Y[j][i] instead of Y[i][j].  X: rows x cols float32 (ldx), Y: ldy in
+ * elements of `dtype`. */
+int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb, const float *D, int64_t ldd,
+                 float *C, int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym,
+                 void *stream);
+int psvt_convert(int dtype, const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y, int64_t ldy,
+                 float scale, int transpose, void *stream);
 
 /* Launch tracing.  psvt_trace_begin() starts recording every kernel launch
  * that the library makes from the calling thread: each is bracketed by two
@@ -141,21 +155,24 @@ int psvt_trace_end(psvt_trace_stat *out, int max_entries, int *n_entries);
  * (1 per CU).  Each product picks the configuration with the smallest
  * modelled time
  *     (most tiles on one CU) x (overhead + tile flops / (eff x CU rate)),
- * with (eff, overhead) per configuration and per kind (sym = 1 for the
- * lower-triangle products, 0 for full ones) measured by the autotuner.
+ * with (eff, overhead) per operand dtype (PSVT_DTYPE_*), kind (sym = 1 for
+ * the lower-triangle products, 0 for full ones) and configuration, measured
+ * by the autotuner.
  *   psvt_tune_force_tile(id)   force a configuration on the calling thread
  *                              (0 = automatic).
- *   psvt_tune_set(id, sym, eff, overhead_us)   eff in (0, 1], overhead >= 0.
- *   psvt_tune_load(path)       read "id sym eff overhead_us" lines ('#'
+ *   psvt_tune_set(dtype, id, sym, eff, overhead_us)  eff in (0, 1],
+ *                              overhead >= 0 microseconds.
+ *   psvt_tune_load(path)       read "dtype id sym eff overhead_us" lines ('#'
  *                              starts a comment); PSVT_EINVAL on a malformed
  *                              line, and then nothing is applied.
  *   psvt_tune_pick             the id the model picks for an M x N x K
  *                              product (>= 1), or a negative error code.
  * The model is process-wide; change it before concurrent calls. */
+enum { PSVT_DTYPE_F32 = 0, PSVT_DTYPE_BF16 = 1, PSVT_DTYPE_FP8 = 2 };
 int psvt_tune_force_tile(int tile);
-int psvt_tune_set(int tile, int sym, double efficiency, double overhead_us);
+int psvt_tune_set(int dtype, int tile, int sym, double efficiency, double overhead_us);
 int psvt_tune_load(const char *path);
-int psvt_tune_pick(int64_t M, int64_t N, int64_t K, int sym);
+int psvt_tune_pick(int dtype, int64_t M, int64_t N, int64_t K, int sym);
 
 /* Static description of a return code. */
 const char *psvt_strerror(int code);

@@ -25,9 +25,10 @@ PSVT_EHIP = -4
 
 OP_SVT, OP_POLAR, OP_POLAR_SYM, OP_RANK_R = 0, 1, 2, 3
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
+DTYPE_F32, DTYPE_BF16, DTYPE_FP8 = 0, 1, 2
 
 EXPORTED = [
-    "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt",
+    "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
     "psvt_strerror", "psvt_last_error", "psvt_version", "psvt_trace_begin", "psvt_trace_end",
     "psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick",
 ]
@@ -79,18 +80,20 @@ def load(path: Optional[str] = None):
     lib.psvt_rank_r.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
     lib.psvt_polar.argtypes = [vp, i64, i64, i64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
     lib.psvt_polar_sym.argtypes = [vp, i64, i64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
-    lib.psvt_gemm_nt.argtypes = [vp, i64, vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.c_float,
+    lib.psvt_gemm_nt.argtypes = [ctypes.c_int, vp, i64, vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_int, vp]
-    for f in ("psvt_workspace_bytes", "psvt_svt", "psvt_rank_r", "psvt_polar", "psvt_polar_sym", "psvt_gemm_nt"):
+    lib.psvt_convert.argtypes = [ctypes.c_int, vp, i64, i64, i64, vp, i64, ctypes.c_float, ctypes.c_int, vp]
+    for f in ("psvt_workspace_bytes", "psvt_svt", "psvt_rank_r", "psvt_polar", "psvt_polar_sym", "psvt_gemm_nt",
+              "psvt_convert"):
         getattr(lib, f).restype = ctypes.c_int
     lib.psvt_strerror.argtypes = [ctypes.c_int]
     lib.psvt_strerror.restype = ctypes.c_char_p
     lib.psvt_last_error.restype = ctypes.c_char_p
     lib.psvt_version.restype = ctypes.c_char_p
     lib.psvt_tune_force_tile.argtypes = [ctypes.c_int]
-    lib.psvt_tune_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    lib.psvt_tune_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     lib.psvt_tune_load.argtypes = [ctypes.c_char_p]
-    lib.psvt_tune_pick.argtypes = [i64, i64, i64, ctypes.c_int]
+    lib.psvt_tune_pick.argtypes = [ctypes.c_int, i64, i64, i64, ctypes.c_int]
     for f in ("psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick"):
         getattr(lib, f).restype = ctypes.c_int
     lib.psvt_trace_begin.restype = ctypes.c_int
@@ -174,6 +177,16 @@ def _ld(A):
     return A.stride(0) if A.stride(0) >= cols and A.stride(0) % 4 == 0 else (cols + 3) // 4 * 4
 
 
+def _ld_any(A):
+    """Row stride in elements for any element size; one-row tensors get a
+    stride that keeps rows 16-byte aligned."""
+    if A.shape[0] > 1:
+        return A.stride(0)
+    per16 = max(1, 16 // A.element_size())
+    cols = max(A.shape[1], 1)
+    return A.stride(0) if A.stride(0) >= cols and A.stride(0) % per16 == 0 else (cols + per16 - 1) // per16 * per16
+
+
 def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
         coeffs=None, out=None, ws=None):
     """A_tau = U max(Sigma - tau I, 0) V^T via Proposition 1 (FP32 out)."""
@@ -247,11 +260,19 @@ def polar_sym(G, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, coeffs=None, 
     return S
 
 
-def gemm_nt(A, B, D=None, alpha: float = 1.0, beta: float = 0.0, sym: bool = False, out=None):
-    """C = alpha A B^T + beta D with the library's FP32 MFMA kernel."""
+_DTYPE_OF = {"float32": DTYPE_F32, "bfloat16": DTYPE_BF16, "uint8": DTYPE_FP8, "float8_e4m3fn": DTYPE_FP8}
+
+
+def gemm_nt(A, B, D=None, alpha: float = 1.0, beta: float = 0.0, sym: bool = False, out=None, dtype=None):
+    """C = alpha A B^T + beta D with the library's MFMA kernel.  A and B hold
+    float32, bfloat16, or FP8 e4m3 bytes (uint8 / float8_e4m3fn tensors)."""
     torch = _torch()
-    _check_input(A)
-    _check_input(B, "B")
+    for X, name in ((A, "A"), (B, "B")):
+        if not isinstance(X, torch.Tensor) or X.ndim != 2 or X.device.type != "cuda" or X.stride(1) != 1:
+            raise TypeError("%s must be a 2-D row-major GPU tensor" % name)
+    dt = _DTYPE_OF.get(str(A.dtype).replace("torch.", "")) if dtype is None else dtype
+    if dt is None or A.dtype != B.dtype:
+        raise TypeError("unsupported operand dtype %s / %s" % (A.dtype, B.dtype))
     M, K = A.shape
     N, K2 = B.shape
     if K != K2:
@@ -259,10 +280,25 @@ def gemm_nt(A, B, D=None, alpha: float = 1.0, beta: float = 0.0, sym: bool = Fal
     C = out if out is not None else torch.empty((M, N), dtype=torch.float32, device=A.device)
     dptr, ldd = (D.data_ptr(), _ld(D)) if D is not None else (None, 0)
     with torch.cuda.device(A.device):
-        _check(load().psvt_gemm_nt(A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), dptr, ldd, C.data_ptr(), _ld(C),
-                                   M, N, K, float(alpha), float(beta), 1 if sym else 0, _stream_ptr(A)),
+        _check(load().psvt_gemm_nt(dt, A.data_ptr(), _ld_any(A), B.data_ptr(), _ld_any(B), dptr, ldd, C.data_ptr(),
+                                   _ld(C), M, N, K, float(alpha), float(beta), 1 if sym else 0, _stream_ptr(A)),
                "psvt_gemm_nt")
     return C
+
+
+def convert(X, dtype: int, scale: float = 1.0, transpose: bool = False, out=None):
+    """Round scale * X (float32) into bfloat16 bits (torch.bfloat16) or FP8
+    e4m3 bytes (torch.uint8), optionally transposed."""
+    torch = _torch()
+    _check_input(X, "X")
+    rows, cols = X.shape
+    shape = (cols, rows) if transpose else (rows, cols)
+    tdt = {DTYPE_F32: torch.float32, DTYPE_BF16: torch.bfloat16, DTYPE_FP8: torch.uint8}[dtype]
+    Y = out if out is not None else torch.empty(shape, dtype=tdt, device=X.device)
+    with torch.cuda.device(X.device):
+        _check(load().psvt_convert(int(dtype), X.data_ptr(), rows, cols, _ld(X), Y.data_ptr(), _ld_any(Y),
+                                   float(scale), 1 if transpose else 0, _stream_ptr(X)), "psvt_convert")
+    return Y
 
 
 def trace_begin():
@@ -284,8 +320,8 @@ def force_tile(tile: int):
     _check(load().psvt_tune_force_tile(int(tile)), "psvt_tune_force_tile")
 
 
-def pick_tile(M: int, N: int, K: int, sym: bool = False) -> int:
-    rc = load().psvt_tune_pick(M, N, K, 1 if sym else 0)
+def pick_tile(M: int, N: int, K: int, sym: bool = False, dtype: int = 0) -> int:
+    rc = load().psvt_tune_pick(int(dtype), M, N, K, 1 if sym else 0)
     if rc < 0:
         _check(rc, "psvt_tune_pick")
     return rc

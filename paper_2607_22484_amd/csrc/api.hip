@@ -113,7 +113,6 @@ int read_cfg(const psvt_config *c, Cfg &out) {
     if (out.coeffs)
         for (int i = 0; i < 3 * out.iters; ++i)
             if (!isfinite(out.coeffs[i])) return fail(PSVT_EINVAL, "coeffs[%d] is not finite", i);
-    if (out.n_fp8 || out.n_bf16) return fail(PSVT_EUNSUPPORTED, "low-precision iterations are not available");
     return PSVT_OK;
 }
 
@@ -122,6 +121,49 @@ void coef(const Cfg &c, int t, float &a, float &b, float &cc) {
     a = (float)p[0];
     b = (float)p[1];
     cc = (float)p[2];
+}
+
+// Operand type of polar iteration t: the first n_fp8 iterations FP8, the
+// next n_bf16 BF16, the rest FP32.
+int iter_dtype(const Cfg &c, int t) {
+    if (t < c.n_fp8) return OP_FP8;
+    if (t < c.n_fp8 + c.n_bf16) return OP_BF16;
+    return OP_F32;
+}
+
+// FP8 operand scales of one iteration: the copies of X (and X^T), of T = X^T X
+// (or X^2) and of B = b T + c T^2 are stored as e4m3(scale * value) and the
+// product is multiplied back by 1 / (scale_A scale_B).  Scales are powers of
+// two chosen from spectral bounds of the iterate, so that no entry exceeds
+// e4m3's largest finite value (448): |entry| <= spectral norm.
+struct IterScale {
+    float sX, sT, sB;
+};
+
+float pow2_scale(double bound) {
+    if (!(bound > 0.0)) return 1.0f;
+    double s = exp2(floor(log2(448.0 / (1.1 * bound))));
+    return (float)fmin(fmax(s, 0x1p-20), 0x1p20);
+}
+
+// U_t bounds the singular values entering iteration t (U_0 = 1 after the
+// theta normalisation); B_t's eigenvalues are b mu + c mu^2 over
+// mu in [0, U_t^2]; the quintic maps [0, U_t] into [-U_{t+1}, U_{t+1}].
+void iteration_scales(const Cfg &c, IterScale *out) {
+    double U = 1.0;
+    for (int t = 0; t <= c.iters; ++t) {
+        float a = 1.875f, b = -1.25f, cc = 0.375f;
+        if (t < c.iters) coef(c, t, a, b, cc);
+        double beta = 0.0, unext = 0.0;
+        const int n = 4096;
+        for (int k = 0; k <= n; ++k) {
+            const double x = 1.05 * U * k / n, mu = x * x;
+            beta = fmax(beta, fabs(b * mu + cc * mu * mu));
+            unext = fmax(unext, fabs(x * (a + b * mu + cc * mu * mu)));
+        }
+        out[t] = IterScale{pow2_scale(U), pow2_scale(U * U), pow2_scale(beta)};
+        U = fmax(unext, 1e-30);
+    }
 }
 
 // ---------------------------------------------------------- workspace
@@ -135,6 +177,9 @@ struct Layout {
     size_t X0 = 0, X0T = 0, Xp = 0, Xq = 0, XTp = 0, XTq = 0;
     size_t T = 0, Bm = 0;
     size_t H = 0, R = 0, S0 = 0, S1 = 0, X2 = 0, BS = 0;
+    // low-precision operand copies (2 bytes per element of room)
+    bool lp = false;
+    size_t XL[2] = {0, 0}, XTL[2] = {0, 0}, TL = 0, BL = 0, SL[2] = {0, 0};
     size_t total = 0;
 };
 
@@ -194,6 +239,18 @@ Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c) {
         L.S1 = take(fS);
         L.X2 = take(fS);
         L.BS = take(fS);
+    }
+    L.lp = c.n_fp8 + c.n_bf16 > 0;
+    if (L.lp) {
+        L.TL = take(fS / 2);
+        L.BL = take(fS / 2);
+        if (need_P)
+            for (int i = 0; i < 2; ++i) {
+                L.XL[i] = take(fX / 2);
+                L.XTL[i] = take(fXT / 2);
+            }
+        if (need_S)
+            for (int i = 0; i < 2; ++i) L.SL[i] = take(fS / 2);
     }
     L.total = off;
     return L;
@@ -288,24 +345,61 @@ int prelude(const float *A, int64_t m, int64_t n, int64_t lda, double tau, const
     return PSVT_OK;
 }
 
+// Low-precision operand settings of one product: operands in `dt` with
+// scales sa, sb; FP32 iterations keep every scale at 1.
+void set_operand_scales(GemmArgs &g, int dt, float sa, float sb) {
+    if (dt != OP_F32) g.ab_scale = 1.0f / (sa * sb);
+}
+
+// Low-precision copies that a product writes for the next consumer.
+void set_lp_out(GemmArgs &g, int type, void *row, int64_t ldrow, void *trans, int64_t ldtrans, float scale) {
+    g.lp_type = type;
+    g.Clp = row;
+    g.ldclp = ldrow;
+    g.CTlp = trans;
+    g.ldctlp = ldtrans;
+    g.lp_scale = scale;
+}
+
 // P iterations.  Result in *out_P (workspace, l x s, ld = ldS) or, when
 // user_out is given, the last iteration writes straight to the caller's
 // buffer (transposed when !L.right).
+//
+// Iteration t in operand type dt keeps the FP32 master X and reads its
+// low-precision copies: T = X^T X (from the copy of X^T), B = c T^2 + b T
+// (from the copy of T, with the FP32 T as the b-term), X' = a X + X B (from
+// the copies of X and B, with the FP32 X as the a-term).  Each product writes
+// the copies its consumer needs, in the consumer's type.
 int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, float *user_out, int64_t ld_out,
                      const float **out_P) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
+    IterScale scl[257];
+    iteration_scales(c, scl);
     const float *curX = F(ws, L.X0), *curXT = F(ws, L.X0T);
+    const void *curXlp = nullptr, *curXTlp = nullptr;
     float *bufX[2] = {F(ws, L.Xp), F(ws, L.Xq)};
     float *bufXT[2] = {F(ws, L.XTp), F(ws, L.XTq)};
+    void *bufXlp[2] = {L.lp ? at(ws, L.XL[0]) : nullptr, L.lp ? at(ws, L.XL[1]) : nullptr};
+    void *bufXTlp[2] = {L.lp ? at(ws, L.XTL[0]) : nullptr, L.lp ? at(ws, L.XTL[1]) : nullptr};
     float *T = F(ws, L.T), *Bm = F(ws, L.Bm);
+    void *Tlp = L.lp ? at(ws, L.TL) : nullptr, *Blp = L.lp ? at(ws, L.BL) : nullptr;
     for (int t = 0; t < c.iters; ++t) {
         float a, b, cc;
         coef(c, t, a, b, cc);
         const bool first = t == 0, last = t == c.iters - 1;
-        if (!first) {
+        const int dt = iter_dtype(c, t), nd = last ? OP_F32 : iter_dtype(c, t + 1);
+        const bool lp = dt != OP_F32;
+        const float sX = dt == OP_FP8 ? scl[t].sX : 1.0f, sT = dt == OP_FP8 ? scl[t].sT : 1.0f,
+                    sB = dt == OP_FP8 ? scl[t].sB : 1.0f, sXn = nd == OP_FP8 ? scl[t + 1].sX : 1.0f;
+        if (first && lp) {
+            // theta is folded into the first copies: X0 / theta and T / theta^2
+            HIP_TRY(launch_convert(curX, L.l, L.s, L.ldS, bufXlp[1], L.ldS, dt, sX, 0, st, sc, F_P1), "P: X0 copy");
+            HIP_TRY(launch_convert(T, L.s, L.s, L.ldS, Tlp, L.ldS, dt, sT, 0, st, sc, F_P2), "P: T copy");
+            curXlp = bufXlp[1];
+        }
+        if (!first) {  // T = X^T X
             GemmArgs g = gemm_defaults();
-            g.A = curXT;
-            g.B = curXT;
+            g.A = g.B = lp ? curXTlp : (const void *)curXT;
             g.lda = g.ldb = L.ldL;
             g.C = T;
             g.ldc = L.ldS;
@@ -313,83 +407,177 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
             g.K = (int)L.l;
             g.sc = sc;
             g.sym = 1;
-            HIP_TRY(launch_gemm(g, OP_F32, st), "P: X^T X");
+            set_operand_scales(g, dt, sX, sX);
+            if (lp) set_lp_out(g, dt, Tlp, L.ldS, nullptr, 0, sT);
+            HIP_TRY(launch_gemm(g, dt, st), "P: X^T X");
         }
-        // Bm = c T^2 + b T   (first iteration: T / theta^2 scaling folded in)
-        HIP_TRY(syrk(T, T, L.ldS, T, Bm, L.ldS, L.s, cc, first ? F_P4 : -1, b, first ? F_P2 : -1, 0.0f, sc, st),
-                "P: b T + c T^2");
-        // X' = a X + X Bm   (first iteration: times 1/theta)
-        GemmArgs g = gemm_defaults();
-        g.A = curX;
-        g.B = Bm;
-        g.lda = L.ldS;
-        g.ldb = L.ldS;
-        g.D = curX;
-        g.ldd = L.ldS;
-        g.M = (int)L.l;
-        g.N = (int)L.s;
-        g.K = (int)L.s;
-        g.alpha = 1.0f;
-        g.i_alpha = first ? F_P1 : -1;
-        g.beta = a;
-        g.i_beta = first ? F_P1 : -1;
-        g.sc = sc;
-        float *nX = bufX[t & 1], *nXT = bufXT[t & 1];
-        if (last && user_out) {
-            if (L.right) {
-                g.C = user_out;
-                g.ldc = ld_out;
+        {  // B = c T^2 + b T   (first iteration: theta scaling through device scalars)
+            GemmArgs g = gemm_defaults();
+            g.A = g.B = lp ? Tlp : (const void *)T;
+            g.lda = g.ldb = L.ldS;
+            g.D = T;
+            g.ldd = L.ldS;
+            g.M = g.N = g.K = (int)L.s;
+            g.alpha = cc;
+            g.i_alpha = (first && !lp) ? F_P4 : -1;
+            g.beta = b;
+            g.i_beta = first ? F_P2 : -1;
+            g.sc = sc;
+            g.sym = 1;
+            set_operand_scales(g, dt, sT, sT);
+            if (lp) {
+                set_lp_out(g, dt, Blp, L.ldS, nullptr, 0, sB);
             } else {
-                g.CT = user_out;
-                g.ldct = ld_out;
+                g.C = Bm;
+                g.ldc = L.ldS;
             }
-        } else {
-            g.C = nX;
-            g.ldc = L.ldS;
-            if (!last) {
-                g.CT = nXT;
-                g.ldct = L.ldL;
-            }
+            HIP_TRY(launch_gemm(g, dt, st), "P: b T + c T^2");
         }
-        HIP_TRY(launch_gemm(g, OP_F32, st), "P: a X + X B");
-        curX = nX;
-        curXT = nXT;
+        {  // X' = a X + X B   (first iteration: times 1/theta)
+            GemmArgs g = gemm_defaults();
+            g.A = lp ? curXlp : (const void *)curX;
+            g.lda = L.ldS;
+            g.B = lp ? (const void *)Blp : (const void *)Bm;
+            g.ldb = L.ldS;
+            g.D = curX;
+            g.ldd = L.ldS;
+            g.M = (int)L.l;
+            g.N = (int)L.s;
+            g.K = (int)L.s;
+            g.alpha = 1.0f;
+            g.i_alpha = (first && !lp) ? F_P1 : -1;
+            g.beta = a;
+            g.i_beta = first ? F_P1 : -1;
+            g.sc = sc;
+            set_operand_scales(g, dt, sX, sB);
+            const int k = t & 1;
+            if (last && user_out) {
+                if (L.right) {
+                    g.C = user_out;
+                    g.ldc = ld_out;
+                } else {
+                    g.CT = user_out;
+                    g.ldct = ld_out;
+                }
+            } else {
+                g.C = bufX[k];
+                g.ldc = L.ldS;
+                if (!last) {
+                    if (nd == OP_F32) {
+                        g.CT = bufXT[k];
+                        g.ldct = L.ldL;
+                    } else {
+                        set_lp_out(g, nd, bufXlp[k], L.ldS, bufXTlp[k], L.ldL, sXn);
+                    }
+                }
+            }
+            HIP_TRY(launch_gemm(g, dt, st), "P: a X + X B");
+            curX = bufX[k];
+            curXT = bufXT[k];
+            curXlp = bufXlp[k];
+            curXTlp = bufXTlp[k];
+        }
     }
     if (out_P) *out_P = curX;
     return PSVT_OK;
 }
 
 // S iterations from H (s x s, ld = ldS) with R = H^2 and theta_S already in
-// the scalar block.  want_pi: the last iteration writes (I + S)/2.
+// the scalar block.  want_pi: the last iteration writes (I + S)/2.  Same
+// precision scheme as the P iterations, with X^2 in place of X^T X.
 int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, bool want_pi, float *user_out,
                     int64_t ld_out, const float **out_S) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
+    IterScale scl[257];
+    iteration_scales(c, scl);
     const int64_t s = L.s, ld = L.ldS;
     const float *cur = F(ws, L.H);
+    const void *curlp = nullptr;
     float *R = F(ws, L.R), *X2 = F(ws, L.X2), *BS = F(ws, L.BS);
     float *buf[2] = {F(ws, L.S0), F(ws, L.S1)};
+    void *buflp[2] = {L.lp ? at(ws, L.SL[0]) : nullptr, L.lp ? at(ws, L.SL[1]) : nullptr};
+    void *X2lp = L.lp ? at(ws, L.TL) : nullptr, *BSlp = L.lp ? at(ws, L.BL) : nullptr;
     for (int t = 0; t < c.iters; ++t) {
         float a, b, cc;
         coef(c, t, a, b, cc);
         const bool first = t == 0, last = t == c.iters - 1;
+        const int dt = iter_dtype(c, t), nd = last ? OP_F32 : iter_dtype(c, t + 1);
+        const bool lp = dt != OP_F32;
+        const float sX = dt == OP_FP8 ? scl[t].sX : 1.0f, sT = dt == OP_FP8 ? scl[t].sT : 1.0f,
+                    sB = dt == OP_FP8 ? scl[t].sB : 1.0f, sXn = nd == OP_FP8 ? scl[t + 1].sX : 1.0f;
+        if (first && lp) {
+            HIP_TRY(launch_convert(cur, s, s, ld, buflp[1], ld, dt, sX, 0, st, sc, F_S1), "S: H copy");
+            HIP_TRY(launch_convert(R, s, s, ld, X2lp, ld, dt, sT, 0, st, sc, F_S2), "S: H^2 copy");
+            curlp = buflp[1];
+        }
         const float *sq = R;
-        if (!first) {
-            HIP_TRY(syrk(cur, cur, ld, nullptr, X2, ld, s, 1.0f, -1, 0.0f, -1, 0.0f, sc, st), "S: X^2");
+        if (!first) {  // X^2
+            GemmArgs g = gemm_defaults();
+            g.A = g.B = lp ? curlp : (const void *)cur;
+            g.lda = g.ldb = ld;
+            g.C = X2;
+            g.ldc = ld;
+            g.M = g.N = g.K = (int)s;
+            g.sc = sc;
+            g.sym = 1;
+            set_operand_scales(g, dt, sX, sX);
+            if (lp) set_lp_out(g, dt, X2lp, ld, nullptr, 0, sT);
+            HIP_TRY(launch_gemm(g, dt, st), "S: X^2");
             sq = X2;
         }
-        HIP_TRY(syrk(sq, sq, ld, sq, BS, ld, s, cc, first ? F_S4 : -1, b, first ? F_S2 : -1, 0.0f, sc, st),
-                "S: b X^2 + c X^4");
-        float alpha = 1.0f, beta = a, diag = 0.0f;
-        if (last && want_pi) {
-            alpha = 0.5f;
-            beta = 0.5f * a;
-            diag = 0.5f;
+        {  // B = c X^4 + b X^2
+            GemmArgs g = gemm_defaults();
+            g.A = g.B = lp ? (const void *)X2lp : (const void *)sq;
+            g.lda = g.ldb = ld;
+            g.D = sq;
+            g.ldd = ld;
+            g.M = g.N = g.K = (int)s;
+            g.alpha = cc;
+            g.i_alpha = (first && !lp) ? F_S4 : -1;
+            g.beta = b;
+            g.i_beta = first ? F_S2 : -1;
+            g.sc = sc;
+            g.sym = 1;
+            set_operand_scales(g, dt, sT, sT);
+            if (lp) {
+                set_lp_out(g, dt, BSlp, ld, nullptr, 0, sB);
+            } else {
+                g.C = BS;
+                g.ldc = ld;
+            }
+            HIP_TRY(launch_gemm(g, dt, st), "S: b X^2 + c X^4");
         }
-        float *dst = (last && user_out) ? user_out : buf[t & 1];
-        const int64_t ldd = (last && user_out) ? ld_out : ld;
-        HIP_TRY(syrk(BS, cur, ld, cur, dst, ldd, s, alpha, first ? F_S1 : -1, beta, first ? F_S1 : -1, diag, sc, st),
-                "S: a X + B X");
-        cur = dst;
+        {  // X' = a X + B X  (symmetric: B and X commute)
+            float alpha = 1.0f, beta = a, diag = 0.0f;
+            if (last && want_pi) {
+                alpha = 0.5f;
+                beta = 0.5f * a;
+                diag = 0.5f;
+            }
+            GemmArgs g = gemm_defaults();
+            g.A = lp ? (const void *)BSlp : (const void *)BS;
+            g.B = lp ? curlp : (const void *)cur;
+            g.lda = g.ldb = ld;
+            g.D = cur;
+            g.ldd = ld;
+            g.M = g.N = g.K = (int)s;
+            g.alpha = alpha;
+            g.i_alpha = (first && !lp) ? F_S1 : -1;
+            g.beta = beta;
+            g.i_beta = first ? F_S1 : -1;
+            g.diag = diag;
+            g.sc = sc;
+            g.sym = 1;
+            set_operand_scales(g, dt, sB, sX);
+            const int k = t & 1;
+            float *dst = (last && user_out) ? user_out : buf[k];
+            g.C = dst;
+            g.ldc = (last && user_out) ? ld_out : ld;
+            if (!last && nd != OP_F32) set_lp_out(g, nd, buflp[k], ld, nullptr, 0, sXn);
+            HIP_TRY(launch_gemm(g, dt, st), "S: a X + B X");
+            cur = dst;
+            curlp = buflp[k];
+        }
     }
     if (out_S) *out_S = cur;
     return PSVT_OK;
@@ -548,9 +736,11 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
     return sign_iterations(c, L, ws, st, false, S, lds, nullptr);
 }
 
-int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const float *D, int64_t ldd, float *C,
-                 int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym, void *stream) {
+int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb, const float *D, int64_t ldd,
+                 float *C, int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym,
+                 void *stream) {
     g_last_error.clear();
+    if (dtype < 0 || dtype > 2) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
     if (M < 0 || N < 0 || K < 0) return fail(PSVT_EINVAL, "negative size");
     if (M == 0 || N == 0) return PSVT_OK;
     if (M > (1LL << 30) || N > (1LL << 30) || K > (1LL << 30)) return fail(PSVT_EINVAL, "size too large");
@@ -558,9 +748,10 @@ int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const
     if (K > 0 && (!A || !B)) return fail(PSVT_EINVAL, "A or B is NULL");
     if (ldc < N || (K > 0 && (lda < K || ldb < K)) || (D && ldd < N)) return fail(PSVT_EINVAL, "bad leading dimension");
     if (sym && M != N) return fail(PSVT_EINVAL, "sym needs M == N");
-    auto al16 = [](const void *p, int64_t ld) { return p == nullptr || (((uintptr_t)p & 15) == 0 && ld % 4 == 0); };
-    if (!al16(A, lda) || !al16(B, ldb) || !al16(C, ldc) || !al16(D, ldd))
-        return fail(PSVT_EINVAL, "operands must be 16-byte aligned with ld a multiple of 4");
+    const int esz = dtype == PSVT_DTYPE_F32 ? 4 : (dtype == PSVT_DTYPE_BF16 ? 2 : 1);
+    auto al16 = [](const void *p, int64_t ldbytes) { return p == nullptr || (((uintptr_t)p & 15) == 0 && ldbytes % 16 == 0); };
+    if (!al16(A, lda * esz) || !al16(B, ldb * esz) || !al16(C, ldc * 4) || !al16(D, ldd * 4))
+        return fail(PSVT_EINVAL, "operands must be 16-byte aligned with 16-byte-multiple row strides");
     int rc = check_device();
     if (rc) return rc;
     GemmArgs g = gemm_defaults();
@@ -578,9 +769,23 @@ int psvt_gemm_nt(const float *A, int64_t lda, const float *B, int64_t ldb, const
     g.alpha = alpha;
     g.beta = beta;
     g.sym = sym ? 1 : 0;
-    Scalars *none = nullptr;
-    g.sc = none;
-    HIP_TRY(launch_gemm(g, OP_F32, (hipStream_t)stream), "gemm");
+    HIP_TRY(launch_gemm(g, dtype, (hipStream_t)stream), "gemm");
+    return PSVT_OK;
+}
+
+int psvt_convert(int dtype, const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y, int64_t ldy,
+                 float scale, int transpose, void *stream) {
+    g_last_error.clear();
+    if (dtype < 0 || dtype > 2) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
+    if (rows < 0 || cols < 0) return fail(PSVT_EINVAL, "negative size");
+    if (rows == 0 || cols == 0) return PSVT_OK;
+    if (!X || !Y) return fail(PSVT_EINVAL, "NULL buffer");
+    if (ldx < cols || ldy < (transpose ? rows : cols)) return fail(PSVT_EINVAL, "bad leading dimension");
+    if (!isfinite(scale)) return fail(PSVT_EINVAL, "scale must be finite");
+    int rc = check_device();
+    if (rc) return rc;
+    HIP_TRY(launch_convert(X, rows, cols, ldx, Y, ldy, dtype, scale, transpose ? 1 : 0, (hipStream_t)stream),
+            "convert");
     return PSVT_OK;
 }
 
@@ -590,9 +795,9 @@ int psvt_tune_force_tile(int tile) {
     return PSVT_OK;
 }
 
-int psvt_tune_set(int tile, int sym, double efficiency, double overhead_us) {
-    if (tune_set_model(tile, sym, (float)efficiency, (float)overhead_us) != 0)
-        return fail(PSVT_EINVAL, "bad tuning entry %d %d %g %g", tile, sym, efficiency, overhead_us);
+int psvt_tune_set(int dtype, int tile, int sym, double efficiency, double overhead_us) {
+    if (tune_set_model(dtype, tile, sym, (float)efficiency, (float)overhead_us) != 0)
+        return fail(PSVT_EINVAL, "bad tuning entry %d %d %d %g %g", dtype, tile, sym, efficiency, overhead_us);
     return PSVT_OK;
 }
 
@@ -601,9 +806,9 @@ int psvt_tune_load(const char *path) {
     FILE *f = fopen(path, "r");
     if (!f) return fail(PSVT_EINVAL, "cannot open %s", path);
     struct Entry {
-        int id, sym;
+        int type, id, sym;
         double e, o;
-    } ent[32];
+    } ent[64];
     char line[256];
     int n = 0, lineno = 0;
     while (fgets(line, sizeof line, f)) {
@@ -612,24 +817,25 @@ int psvt_tune_load(const char *path) {
         if (hash) *hash = 0;
         Entry e;
         char extra[8];
-        const int got = sscanf(line, "%d %d %lf %lf %7s", &e.id, &e.sym, &e.e, &e.o, extra);
+        const int got = sscanf(line, "%d %d %d %lf %lf %7s", &e.type, &e.id, &e.sym, &e.e, &e.o, extra);
         if (got <= 0) continue;  // blank or comment
-        if (got != 4 || e.id < 1 || e.id > 4 || (e.sym != 0 && e.sym != 1) || !(e.e > 0.0 && e.e <= 1.0) ||
-            !(e.o >= 0.0 && e.o < 1e6) || n >= 32) {
+        if (got != 5 || e.type < 0 || e.type > 2 || e.id < 1 || e.id > 4 || (e.sym != 0 && e.sym != 1) ||
+            !(e.e > 0.0 && e.e <= 1.0) || !(e.o >= 0.0 && e.o < 1e6) || n >= 64) {
             fclose(f);
-            return fail(PSVT_EINVAL, "%s:%d: expected 'id sym efficiency overhead_us'", path, lineno);
+            return fail(PSVT_EINVAL, "%s:%d: expected 'dtype id sym efficiency overhead_us'", path, lineno);
         }
         ent[n++] = e;
     }
     fclose(f);
-    for (int i = 0; i < n; ++i) tune_set_model(ent[i].id, ent[i].sym, (float)ent[i].e, (float)ent[i].o);
+    for (int i = 0; i < n; ++i) tune_set_model(ent[i].type, ent[i].id, ent[i].sym, (float)ent[i].e, (float)ent[i].o);
     return PSVT_OK;
 }
 
-int psvt_tune_pick(int64_t M, int64_t N, int64_t K, int sym) {
+int psvt_tune_pick(int dtype, int64_t M, int64_t N, int64_t K, int sym) {
+    if (dtype < 0 || dtype > 2) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
     if (M <= 0 || N <= 0 || K < 0 || M > (1LL << 30) || N > (1LL << 30) || K > (1LL << 30))
         return fail(PSVT_EINVAL, "bad size");
-    return tune_pick((int)M, (int)N, (int)K, sym ? 1 : 0);
+    return tune_pick(dtype, (int)M, (int)N, (int)K, sym ? 1 : 0);
 }
 
 const char *psvt_strerror(int code) {

@@ -73,8 +73,10 @@ hipError_t launch_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, i
                              hipStream_t st);
 hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, int64_t ldh,
                                    const Scalars *sc, hipStream_t st);
+// Y = round(scale * [sc->f[i_scale]] * X) in op_type, optionally transposed.
 hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy,
-                          int op_type, float scale, int transpose, hipStream_t st);
+                          int op_type, float scale, int transpose, hipStream_t st, const Scalars *sc = nullptr,
+                          int i_scale = -1);
 
 // modes for launch_fro_norm
 enum NormMode {
@@ -88,7 +90,7 @@ constexpr int NORM_PARTIALS = 1024;
 
 // Tile-configuration control (autotuner and tests).
 void tune_force_tile(int c);
-int tune_set_model(int c, int sym, float e, float overhead_us);
-int tune_pick(int M, int N, int K, int sym);
+int tune_set_model(int type, int c, int sym, float e, float overhead_us);
+int tune_pick(int type, int M, int N, int K, int sym);
 
 }  // namespace psvt

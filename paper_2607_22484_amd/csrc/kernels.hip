@@ -27,6 +27,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <utility>
+
 #include "kernels.h"
 #include "trace.h"
 
@@ -34,6 +36,16 @@ namespace psvt {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <typename F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+// f(0), f(1), ..., f(N-1) with compile-time constant arguments
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 __device__ __forceinline__ float scal(const Scalars *sc, int idx) { return idx >= 0 ? sc->f[idx] : 1.0f; }
 
@@ -69,17 +81,148 @@ __device__ __forceinline__ void grouped_index(int t, int nbm, int nbn, int &bi, 
     bj = in / gsize;
 }
 
-// ------------------------------------------------------------- FP32 GEMM
+// --------------------------------------------------------- operand types
+
+// Storage of one GEMM operand.  Every type moves in 16-byte chunks; an LDS
+// row holds 8 chunks (128 bytes) of the k dimension plus a 16-byte pad.
+template <int ET>
+struct Op;
+template <>
+struct Op<OP_F32> {
+    typedef float T;
+    static constexpr int EPC = 4;  // elements per 16-byte chunk
+};
+template <>
+struct Op<OP_BF16> {
+    typedef uint16_t T;
+    static constexpr int EPC = 8;
+};
+template <>
+struct Op<OP_FP8> {
+    typedef uint8_t T;
+    static constexpr int EPC = 16;
+};
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+// float -> bfloat16, round to nearest even (inputs are finite)
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// float -> OCP FP8 e4m3 (gfx950 hardware conversion, round to nearest even),
+// saturated to the largest finite value 448.
+__device__ __forceinline__ uint8_t to_fp8(float x) {
+    x = fminf(fmaxf(x, -448.0f), 448.0f);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF);
+}
+
+__device__ __forceinline__ void store_lp(void *base, int type, int64_t idx, float v) {
+    if (type == OP_BF16)
+        ((uint16_t *)base)[idx] = to_bf16(v);
+    else
+        ((uint8_t *)base)[idx] = to_fp8(v);
+}
+
+// One MFMA step pair over 32 bytes of k per lane (two 16-byte chunks).
+template <int ET>
+__device__ __forceinline__ floatx16 mfma_32b(const u32x4 &a0, const u32x4 &a1, const u32x4 &b0, const u32x4 &b1,
+                                             floatx16 acc) {
+    if constexpr (ET == OP_F32) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a0[e]), __uint_as_float(b0[e]), acc, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a1[e]), __uint_as_float(b1[e]), acc, 0, 0, 0);
+    } else if constexpr (ET == OP_BF16) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0),
+                                                      acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a1), __builtin_bit_cast(bf16x8, b1),
+                                                      acc, 0, 0, 0);
+    } else {
+        const intx8 a = {(int)a0[0], (int)a0[1], (int)a0[2], (int)a0[3], (int)a1[0], (int)a1[1], (int)a1[2], (int)a1[3]};
+        const intx8 b = {(int)b0[0], (int)b0[1], (int)b0[2], (int)b0[3], (int)b1[0], (int)b1[1], (int)b1[2], (int)b1[3]};
+        // format 0 = FP8 e4m3 for both operands, unit scales (E8M0 127 = 2^0)
+        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
+    }
+    return acc;
+}
+
+// Epilogue for one lane's 4 consecutive rows ib..ib+3 of column j:
+// v = alpha acc (given) + beta D + diag [i == j], then the FP32 outputs C/CT
+// and the low-precision copies Clp/CTlp (value * lp_scale).  SYM: only
+// i >= j is kept on diagonal tiles and every kept i != j is also written to
+// the mirrored position [j][i].
+template <bool SYM>
+__device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j, float v[4], float beta,
+                                               bool diag_tile) {
+    bool wr[4], mir[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = ib + e;
+        if (beta != 0.0f && i < g.M) v[e] += beta * g.D[(int64_t)i * g.ldd + j];
+        if (i == j) v[e] += g.diag;
+        wr[e] = i < g.M && (!diag_tile || i >= j);
+        mir[e] = SYM && wr[e] && i != j;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (!wr[e]) continue;
+        const int64_t i = ib + e;
+        if (g.C) g.C[i * g.ldc + j] = v[e];
+        if (g.Clp) store_lp(g.Clp, g.lp_type, i * g.ldclp + j, v[e] * g.lp_scale);
+    }
+    float *ct = SYM ? g.C : g.CT;
+    const int64_t ldct = SYM ? g.ldc : g.ldct;
+    const int ctv = SYM ? g.c_vec : g.ct_vec;
+    bool t[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[e] = SYM ? mir[e] : (ib + e < g.M);
+    if (ct) {
+        float *p = ct + (int64_t)j * ldct + ib;
+        if (ctv && t[0] && t[1] && t[2] && t[3]) {
+            *(floatx4 *)p = floatx4{v[0], v[1], v[2], v[3]};
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t[e]) p[e] = v[e];
+        }
+    }
+    void *ctl = SYM ? g.Clp : g.CTlp;
+    const int64_t ldctl = SYM ? g.ldclp : g.ldctlp;
+    if (ctl) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (t[e]) store_lp(ctl, g.lp_type, (int64_t)j * ldctl + ib + e, v[e] * g.lp_scale);
+    }
+}
+
+// ------------------------------------------------------------------ GEMM
 
 // BM x BN block tile, 256 threads = 2 x 2 waves, each wave (BM/2) x (BN/2)
-// made of TM x TN 32x32 MFMA blocks.  BK = 32 floats.
-template <int BM, int BN, int OCC, bool TWO_A, bool SYM>
-__global__ __launch_bounds__(256, OCC) void gemm_nt_f32(GemmArgs g) {
-    constexpr int BK = 32;
-    constexpr int LDS = BK + 4;  // row stride in floats (144 bytes)
+// made of TM x TN 32x32 MFMA blocks.  A k-tile is 128 bytes of every row
+// (32 floats, 64 bf16 or 128 fp8).
+//
+// MFMA lane layouts (32x32 blocks): lane l feeds row l%32 of A and of B
+// (B given as B^T rows) with k-slot group l/32, and holds output
+// C[8(r/4) + 4(l/32) + r%4][l%32] in accumulator register r.  The sum over k
+// is order-free, so lane half h takes bytes [64h, 64h + 64) of its rows in
+// every k-tile: four 16-byte LDS reads per row.  f32 feeds 1 element per
+// MFMA (16 MFMAs per k-tile), bf16 8 (4 MFMAs), fp8 32 (2 MFMAs).
+template <int ET, int BM, int BN, int OCC, bool TWO_A, bool SYM>
+__global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
+    typedef typename Op<ET>::T T;
+    constexpr int EPC = Op<ET>::EPC;
+    constexpr int BK = 8 * EPC;        // elements per k-tile
+    constexpr int ROWB = 144;          // LDS row stride in bytes
     constexpr int TM = BM / 64, TN = BN / 64;
     constexpr int RA = BM / 32, RB = BN / 32;  // 16-byte loads per thread
-    __shared__ __attribute__((aligned(16))) float smem[2 * (BM + BN) * LDS];
+    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * (BM + BN) * ROWB];
 
     const int nbm = (g.M + BM - 1) / BM, nbn = (g.N + BN - 1) / BN;
     int bi, bj;
@@ -94,25 +237,38 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt_f32(GemmArgs g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
-    const float *A = (const float *)g.A;
-    const float *A2 = (const float *)g.A2;
-    const float *B = (const float *)g.B;
-    const float wa = g.wa * scal(g.sc, g.i_wa);
-    const float wa2 = TWO_A ? g.wa2 * scal(g.sc, g.i_wa2) : 0.0f;
+    const T *A = (const T *)g.A;
+    const T *A2 = (const T *)g.A2;
+    const T *B = (const T *)g.B;
+    float wa = 1.0f, wa2 = 0.0f;
+    if constexpr (ET == OP_F32) {
+        wa = g.wa * scal(g.sc, g.i_wa);
+        wa2 = TWO_A ? g.wa2 * scal(g.sc, g.i_wa2) : 0.0f;
+    }
 
-    const int lrow = tid >> 3, lk = (tid & 7) * 4;
-    floatx4 ra[RA], rb[RB];
+    const int lrow = tid >> 3, lchunk = tid & 7;
+    u32x4 ra[RA], rb[RB];
 
-    auto load_row = [&](const float *P, int64_t ld, int row, int rows, int k) -> floatx4 {
-        floatx4 v = {0.f, 0.f, 0.f, 0.f};
+    auto load_chunk = [&](const T *P, int64_t ld, int row, int rows, int k) -> u32x4 {
+        u32x4 v = {0u, 0u, 0u, 0u};
         if (row < rows) {
-            const float *p = P + (int64_t)row * ld + k;
-            if (k + 3 < g.K) {
-                v = *(const floatx4 *)p;
+            const T *p = P + (int64_t)row * ld + k;
+            if (k + EPC <= g.K) {
+                v = *(const u32x4 *)p;
             } else {
-                if (k + 0 < g.K) v.x = p[0];
-                if (k + 1 < g.K) v.y = p[1];
-                if (k + 2 < g.K) v.z = p[2];
+                // ragged k tail: element-wise, zero beyond K
+#pragma unroll
+                for (int e = 0; e < EPC; ++e) {
+                    uint32_t x = 0u;
+                    if (k + e < g.K) {
+                        if constexpr (ET == OP_F32)
+                            x = __float_as_uint(p[e]);
+                        else
+                            x = (uint32_t)p[e];
+                    }
+                    constexpr int SZ = (int)sizeof(T);
+                    v[(e * SZ) / 4] |= x << (8 * ((e * SZ) % 4));
+                }
             }
         }
         return v;
@@ -121,25 +277,30 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt_f32(GemmArgs g) {
 #pragma unroll
         for (int p = 0; p < RA; ++p) {
             const int r = lrow + 32 * p;
-            floatx4 v = load_row(A, g.lda, i0 + r, g.M, k0 + lk);
-            if (TWO_A) {
-                floatx4 v2 = load_row(A2, g.lda2, i0 + r, g.M, k0 + lk);
-                v = wa * v + wa2 * v2;
-            } else {
-                v = wa * v;
+            u32x4 v = load_chunk(A, g.lda, i0 + r, g.M, k0 + lchunk * EPC);
+            if constexpr (ET == OP_F32) {
+                floatx4 f = __builtin_bit_cast(floatx4, v);
+                if (TWO_A) {
+                    const floatx4 f2 =
+                        __builtin_bit_cast(floatx4, load_chunk(A2, g.lda2, i0 + r, g.M, k0 + lchunk * EPC));
+                    f = wa * f + wa2 * f2;
+                } else {
+                    f = wa * f;
+                }
+                v = __builtin_bit_cast(u32x4, f);
             }
             ra[p] = v;
         }
 #pragma unroll
-        for (int p = 0; p < RB; ++p) rb[p] = load_row(B, g.ldb, j0 + lrow + 32 * p, g.N, k0 + lk);
+        for (int p = 0; p < RB; ++p) rb[p] = load_chunk(B, g.ldb, j0 + lrow + 32 * p, g.N, k0 + lchunk * EPC);
     };
     auto sstore = [&](int buf) {
-        float *As = smem + buf * (BM + BN) * LDS;
-        float *Bs = As + BM * LDS;
+        uint8_t *As = smem + buf * (BM + BN) * ROWB;
+        uint8_t *Bs = As + BM * ROWB;
 #pragma unroll
-        for (int p = 0; p < RA; ++p) *(floatx4 *)&As[(lrow + 32 * p) * LDS + lk] = ra[p];
+        for (int p = 0; p < RA; ++p) *(u32x4 *)&As[(lrow + 32 * p) * ROWB + lchunk * 16] = ra[p];
 #pragma unroll
-        for (int p = 0; p < RB; ++p) *(floatx4 *)&Bs[(lrow + 32 * p) * LDS + lk] = rb[p];
+        for (int p = 0; p < RB; ++p) *(u32x4 *)&Bs[(lrow + 32 * p) * ROWB + lchunk * 16] = rb[p];
     };
 
     floatx16 acc[TM][TN];
@@ -158,22 +319,26 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt_f32(GemmArgs g) {
     for (int kt = 0; kt < nk; ++kt) {
         const int buf = kt & 1;
         if (kt + 1 < nk) gload((kt + 1) * BK);
-        const float *As = smem + buf * (BM + BN) * LDS + (wm * (BM / 2)) * LDS;
-        const float *Bs = smem + buf * (BM + BN) * LDS + BM * LDS + (wn * (BN / 2)) * LDS;
+        const uint8_t *As = smem + buf * (BM + BN) * ROWB + (wm * (BM / 2)) * ROWB + fh * 64;
+        const uint8_t *Bs = smem + buf * (BM + BN) * ROWB + BM * ROWB + (wn * (BN / 2)) * ROWB + fh * 64;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            floatx4 af[TM], bf[TN];
+        for (int q = 0; q < 2; ++q) {
+            u32x4 af[TM][2], bf[TN][2];
 #pragma unroll
-            for (int a = 0; a < TM; ++a) af[a] = *(const floatx4 *)&As[(a * 32 + frow) * LDS + fh * 16 + q * 4];
+            for (int a = 0; a < TM; ++a) {
+                af[a][0] = *(const u32x4 *)&As[(a * 32 + frow) * ROWB + q * 32];
+                af[a][1] = *(const u32x4 *)&As[(a * 32 + frow) * ROWB + q * 32 + 16];
+            }
 #pragma unroll
-            for (int b = 0; b < TN; ++b) bf[b] = *(const floatx4 *)&Bs[(b * 32 + frow) * LDS + fh * 16 + q * 4];
+            for (int b = 0; b < TN; ++b) {
+                bf[b][0] = *(const u32x4 *)&Bs[(b * 32 + frow) * ROWB + q * 32];
+                bf[b][1] = *(const u32x4 *)&Bs[(b * 32 + frow) * ROWB + q * 32 + 16];
+            }
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int a = 0; a < TM; ++a)
 #pragma unroll
-                for (int a = 0; a < TM; ++a)
-#pragma unroll
-                    for (int b = 0; b < TN; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a][e], bf[b][e], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < TN; ++b)
+                    acc[a][b] = mfma_32b<ET>(af[a][0], af[a][1], bf[b][0], bf[b][1], acc[a][b]);
         }
         if (kt + 1 < nk) sstore(buf ^ 1);
         __syncthreads();
@@ -183,107 +348,71 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt_f32(GemmArgs g) {
     const float alpha = g.alpha * scal(g.sc, g.i_alpha) * g.ab_scale;
     const float beta = g.D ? g.beta * scal(g.sc, g.i_beta) : 0.0f;
     const bool diag_tile = SYM && (bi == bj);
-#pragma unroll
-    for (int a = 0; a < TM; ++a) {
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
+    // compile-time loops: the accumulator array must only ever be indexed
+    // with constants, or it leaves the register file
+    static_for<TM>([&](auto a) {
+        static_for<TN>([&](auto b) {
             const int j = j0 + wn * (BN / 2) + b * 32 + frow;
-#pragma unroll
-            for (int rg = 0; rg < 4; ++rg) {
+            const bool jok = j < g.N;
+            static_for<4>([&](auto rg) {
                 const int ib = i0 + wm * (BM / 2) + a * 32 + rg * 8 + fh * 4;  // rows ib .. ib+3
                 float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int i = ib + e;
-                    float x = alpha * acc[a][b][rg * 4 + e];
-                    if (beta != 0.0f && i < g.M && j < g.N) x += beta * g.D[(int64_t)i * g.ldd + j];
-                    if (i == j) x += g.diag;
-                    v[e] = x;
-                }
-                if (j >= g.N) continue;
-                if (!SYM) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (ib + e < g.M && g.C) g.C[(int64_t)(ib + e) * g.ldc + j] = v[e];
-                    if (g.CT) {
-                        float *p = g.CT + (int64_t)j * g.ldct + ib;
-                        if (g.ct_vec && ib + 3 < g.M) {
-                            *(floatx4 *)p = floatx4{v[0], v[1], v[2], v[3]};
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                if (ib + e < g.M) p[e] = v[e];
-                        }
-                    }
-                } else if (!diag_tile) {
-                    // strictly lower tile: every (i, j) has i > j
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (ib + e < g.M) g.C[(int64_t)(ib + e) * g.ldc + j] = v[e];
-                    float *p = g.C + (int64_t)j * g.ldc + ib;
-                    if (g.c_vec && ib + 3 < g.M) {
-                        *(floatx4 *)p = floatx4{v[0], v[1], v[2], v[3]};
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (ib + e < g.M) p[e] = v[e];
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int i = ib + e;
-                        if (i >= g.M || i < j) continue;
-                        g.C[(int64_t)i * g.ldc + j] = v[e];
-                        if (i != j) g.C[(int64_t)j * g.ldc + i] = v[e];
-                    }
-                }
-            }
-        }
-    }
+                static_for<4>([&](auto e) { v[e] = alpha * acc[a][b][rg * 4 + e]; });
+                if (jok) epilogue_store<SYM>(g, ib, j, v, beta, diag_tile);
+            });
+        });
+    });
 }
 
-// Tile configurations of the FP32 kernel: block tile, blocks per CU.
+// ------------------------------------------------------------ launching
+
+// Tile configurations: block tile, blocks per CU.
 struct TileCfg {
     int bm, occ;
     const char *tag;
 };
 static const TileCfg kTiles[] = {{0, 0, ""}, {64, 4, "64"}, {128, 2, "128"}, {192, 1, "192"}, {256, 1, "256"}};
 constexpr int kNumTiles = 4;
+static const char *kTypeTag[3] = {"f32", "bf16", "fp8"};
+// dense MFMA flop/s of one CU per operand type (257 = 256 CUs + 1)
+static const double kCuRate[3] = {157.3e12 / 256.0, 2516.6e12 / 256.0, 5033.2e12 / 256.0};
 
-// Cost model of one product in configuration c (sym = lower-triangle
-// product or full one):  time ~= (most tiles on one CU) x (overhead +
-// tile flops / (efficiency x CU FP32 MFMA rate)).  The efficiency and the
-// per-tile overhead (prologue/epilogue, in microseconds) come from the
-// autotuner's table (psvt_tune_set / psvt_tune_load); these defaults are a
-// measured starting point.
+// Cost model of one product in configuration c:  time ~= (most tiles on one
+// CU) x (overhead + tile flops / (efficiency x CU MFMA rate)), with the
+// efficiency and per-tile overhead (microseconds) per operand type, kind
+// (sym = lower-triangle product) and configuration, from the autotuner's
+// table (psvt_tune_set / psvt_tune_load).  Defaults: a measured start.
 struct TileModel {
     float eff, overhead_us;
 };
-static TileModel g_model[2][kNumTiles + 1] = {
-    {{0.f, 0.f}, {0.60f, 4.0f}, {0.72f, 6.0f}, {0.71f, 8.0f}, {0.77f, 10.0f}},
-    {{0.f, 0.f}, {0.60f, 4.0f}, {0.70f, 6.0f}, {0.71f, 8.0f}, {0.45f, 10.0f}},
+static TileModel g_model[3][2][kNumTiles + 1] = {
+    {{{0.f, 0.f}, {0.78f, 19.0f}, {0.86f, 51.0f}, {0.73f, 17.0f}, {0.76f, 0.0f}},
+     {{0.f, 0.f}, {0.64f, 14.0f}, {0.72f, 20.0f}, {0.72f, 15.0f}, {0.45f, 19.0f}}},
+    {{{0.f, 0.f}, {0.30f, 6.0f}, {0.40f, 8.0f}, {0.40f, 10.0f}, {0.45f, 12.0f}},
+     {{0.f, 0.f}, {0.30f, 6.0f}, {0.40f, 8.0f}, {0.40f, 10.0f}, {0.45f, 12.0f}}},
+    {{{0.f, 0.f}, {0.25f, 6.0f}, {0.35f, 8.0f}, {0.35f, 10.0f}, {0.40f, 12.0f}},
+     {{0.f, 0.f}, {0.25f, 6.0f}, {0.35f, 8.0f}, {0.35f, 10.0f}, {0.40f, 12.0f}}},
 };
 static thread_local int g_force_tile = 0;
-constexpr double kCuRate = 157.3e12 / 256.0;  // FP32 MFMA flop/s of one CU
 
-int tile_count(const GemmArgs &g, int bm) {
-    const int nbm = (g.M + bm - 1) / bm, nbn = (g.N + bm - 1) / bm;
-    return g.sym ? nbm * (nbm + 1) / 2 : nbm * nbn;
+static int tile_count(int M, int N, int sym, int bm) {
+    const int nbm = (M + bm - 1) / bm, nbn = (N + bm - 1) / bm;
+    return sym ? nbm * (nbm + 1) / 2 : nbm * nbn;
 }
 
-double model_time_us(const GemmArgs &g, int c) {
+static double model_time_us(int type, int M, int N, int K, int sym, int c) {
     const double bm = kTiles[c].bm;
-    const double per_cu = ceil(tile_count(g, kTiles[c].bm) / 256.0);
-    const TileModel &tm = g_model[g.sym ? 1 : 0][c];
-    return per_cu * (tm.overhead_us + 1e6 * bm * bm * 2.0 * g.K / (tm.eff * kCuRate));
+    const double per_cu = ceil(tile_count(M, N, sym, kTiles[c].bm) / 256.0);
+    const TileModel &tm = g_model[type][sym ? 1 : 0][c];
+    return per_cu * (tm.overhead_us + 1e6 * bm * bm * 2.0 * K / (tm.eff * kCuRate[type]));
 }
 
-int pick_tile(const GemmArgs &g) {
+static int pick_tile(int type, int M, int N, int K, int sym) {
     if (g_force_tile >= 1 && g_force_tile <= kNumTiles) return g_force_tile;
     double best = 1e300;
     int arg = 2;
     for (int c = 1; c <= kNumTiles; ++c) {
-        const double t = model_time_us(g, c);
+        const double t = model_time_us(type, M, N, K, sym, c);
         if (t < best * 0.999) {
             best = t;
             arg = c;
@@ -292,22 +421,32 @@ int pick_tile(const GemmArgs &g) {
     return arg;
 }
 
-template <int BM, int OCC>
-static hipError_t launch_f32(const GemmArgs &g, hipStream_t st, const char *tag) {
-    const int nblocks = tile_count(g, BM);
+template <int ET, int BM, int OCC>
+static hipError_t launch_cfg(const GemmArgs &g, hipStream_t st, const char *tag) {
+    const int nblocks = tile_count(g.M, g.N, g.sym, BM);
     if (nblocks == 0) return hipSuccess;
     // useful flops: a symmetric product counts its lower triangle only
     const double flops = g.sym ? (double)g.M * (g.M + 1) * g.K : 2.0 * g.M * g.N * g.K;
-    char name[32];
-    snprintf(name, sizeof name, "%s_f32_%s", g.sym ? "syrk" : (g.A2 ? "gemm2" : "gemm"), tag);
+    char name[40];
+    snprintf(name, sizeof name, "%s_%s_%s", g.sym ? "syrk" : (g.A2 ? "gemm2" : "gemm"), kTypeTag[ET], tag);
     TraceScope tr(st, trace_name(name), flops, 0.0);
     if (g.sym)
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BM, OCC, false, true>), dim3(nblocks), dim3(256), 0, st, g);
-    else if (g.A2)
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BM, OCC, true, false>), dim3(nblocks), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_nt<ET, BM, BM, OCC, false, true>), dim3(nblocks), dim3(256), 0, st, g);
+    else if (ET == OP_F32 && g.A2)
+        hipLaunchKernelGGL((gemm_nt<ET, BM, BM, OCC, ET == OP_F32, false>), dim3(nblocks), dim3(256), 0, st, g);
     else
-        hipLaunchKernelGGL((gemm_nt_f32<BM, BM, OCC, false, false>), dim3(nblocks), dim3(256), 0, st, g);
+        hipLaunchKernelGGL((gemm_nt<ET, BM, BM, OCC, false, false>), dim3(nblocks), dim3(256), 0, st, g);
     return hipGetLastError();
+}
+
+template <int ET>
+static hipError_t launch_type(const GemmArgs &g, hipStream_t st) {
+    switch (pick_tile(ET, g.M, g.N, g.K, g.sym)) {
+        case 1: return launch_cfg<ET, 64, 4>(g, st, "64");
+        case 3: return launch_cfg<ET, 192, 1>(g, st, "192");
+        case 4: return launch_cfg<ET, 256, 1>(g, st, "256");
+        default: return launch_cfg<ET, 128, 2>(g, st, "128");
+    }
 }
 
 hipError_t launch_gemm(const GemmArgs &g_in, int op_type, hipStream_t st) {
@@ -315,32 +454,24 @@ hipError_t launch_gemm(const GemmArgs &g_in, int op_type, hipStream_t st) {
     GemmArgs g = g_in;
     g.c_vec = g.C && ((uintptr_t)g.C & 15) == 0 && g.ldc % 4 == 0;
     g.ct_vec = g.CT && ((uintptr_t)g.CT & 15) == 0 && g.ldct % 4 == 0;
-    if (op_type != OP_F32) return hipErrorInvalidValue;
-    switch (pick_tile(g)) {
-        case 1: return launch_f32<64, 4>(g, st, "64");
-        case 3: return launch_f32<192, 1>(g, st, "192");
-        case 4: return launch_f32<256, 1>(g, st, "256");
-        default: return launch_f32<128, 2>(g, st, "128");
+    if (op_type != OP_F32 && g.A2) return hipErrorInvalidValue;
+    switch (op_type) {
+        case OP_F32: return launch_type<OP_F32>(g, st);
+        case OP_BF16: return launch_type<OP_BF16>(g, st);
+        case OP_FP8: return launch_type<OP_FP8>(g, st);
+        default: return hipErrorInvalidValue;
     }
 }
 
 void tune_force_tile(int c) { g_force_tile = c; }
-int tune_set_model(int c, int sym, float e, float overhead_us) {
-    if (c < 1 || c > kNumTiles || (sym != 0 && sym != 1) || !(e > 0.0f && e <= 1.0f) ||
+int tune_set_model(int type, int c, int sym, float e, float overhead_us) {
+    if (type < 0 || type > 2 || c < 1 || c > kNumTiles || (sym != 0 && sym != 1) || !(e > 0.0f && e <= 1.0f) ||
         !(overhead_us >= 0.0f && overhead_us < 1e6f))
         return -1;
-    g_model[sym][c] = TileModel{e, overhead_us};
+    g_model[type][sym][c] = TileModel{e, overhead_us};
     return 0;
 }
-int tune_pick(int M, int N, int K, int sym) {
-    GemmArgs g;
-    memset(&g, 0, sizeof g);
-    g.M = M;
-    g.N = N;
-    g.K = K;
-    g.sym = sym;
-    return pick_tile(g);
-}
+int tune_pick(int type, int M, int N, int K, int sym) { return pick_tile(type, M, N, K, sym); }
 
 // ---------------------------------------------------------------- norms
 
@@ -498,9 +629,51 @@ hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float
     return hipGetLastError();
 }
 
-hipError_t launch_convert(const float *, int64_t, int64_t, int64_t, void *, int64_t, int, float, int,
-                          hipStream_t) {
-    return hipErrorInvalidValue;  // low-precision copies: not built yet
+// Y = round(scale * X) in `type`, optionally transposed.  64 x 64 tiles
+// through LDS so that both the reads and the writes are row-contiguous.
+__global__ __launch_bounds__(256) void convert_tile(const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y,
+                                                    int64_t ldy, int type, float scale0, int transpose,
+                                                    const Scalars *sc, int i_scale) {
+    __shared__ float tile[64][65];
+    const float scale = scale0 * (sc ? scal(sc, i_scale) : 1.0f);
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int k = ty; k < 64; k += 4) {
+        const int64_t r = r0 + k, c = c0 + tx;
+        const float v = (r < rows && c < cols) ? scale * X[r * ldx + c] : 0.0f;
+        if (!transpose) {
+            if (r < rows && c < cols) {
+                if (type == OP_F32)
+                    ((float *)Y)[r * ldy + c] = v;
+                else
+                    store_lp(Y, type, r * ldy + c, v);
+            }
+        } else {
+            tile[k][tx] = v;
+        }
+    }
+    if (!transpose) return;
+    __syncthreads();
+    for (int k = ty; k < 64; k += 4) {
+        const int64_t c = c0 + k, r = r0 + tx;  // Y[c][r] = X[r][c]
+        if (c < cols && r < rows) {
+            if (type == OP_F32)
+                ((float *)Y)[c * ldy + r] = tile[tx][k];
+            else
+                store_lp(Y, type, c * ldy + r, tile[tx][k]);
+        }
+    }
+}
+
+hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y, int64_t ldy, int type,
+                          float scale, int transpose, hipStream_t st, const Scalars *sc, int i_scale) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (type < 0 || type > 2) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+    TraceScope tr(st, "convert", 0.0, (double)rows * cols * (4.0 + (type == OP_F32 ? 4 : type == OP_BF16 ? 2 : 1)));
+    hipLaunchKernelGGL(convert_tile, grid, dim3(256), 0, st, X, rows, cols, ldx, Y, ldy, type, scale, transpose, sc,
+                       i_scale);
+    return hipGetLastError();
 }
 
 }  // namespace psvt

@@ -53,7 +53,7 @@ TraceScope::TraceScope(hipStream_t st, const char *name, double flops, double by
     if (!g_state.on) return;
     start_ = g_state.get();
     stop_ = g_state.get();
-    if (start_) hipEventRecord(start_, st_);
+    if (start_) (void)hipEventRecord(start_, st_);
 }
 
 TraceScope::~TraceScope() {
@@ -62,7 +62,7 @@ TraceScope::~TraceScope() {
         if (stop_) g_state.pool.push_back(stop_);
         return;
     }
-    hipEventRecord(stop_, st_);
+    (void)hipEventRecord(stop_, st_);
     g_state.recs.push_back(Rec{name_, flops_, bytes_, start_, stop_});
 }
 

@@ -86,10 +86,10 @@ def fit(rows):
 
 def write_table(path, table):
     with open(path, "w") as f:
-        f.write("# id sym efficiency overhead_us  (fitted by paper_2607_22484_amd.tune on one MI355X)\n")
-        for (t, sym) in sorted(table):
-            e, o = table[(t, sym)]
-            f.write("%d %d %.4f %.2f\n" % (t, sym, e, o))
+        f.write("# dtype id sym efficiency overhead_us  (fitted by paper_2607_22484_amd.tune on one MI355X)\n")
+        for key in sorted(table):
+            e, o = table[key]
+            f.write("%d %d %d %.4f %.2f\n" % (key + (e, o)))
 
 
 def main():

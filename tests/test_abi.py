@@ -96,9 +96,13 @@ def test_other_entry_points_validate():
     assert lib.psvt_polar(FAKE, 5, 4, 3, FAKE, 4, FAKE, 1 << 30, None, None) == psvt.PSVT_EINVAL
     assert lib.psvt_polar_sym(FAKE, 5, 4, FAKE, 5, FAKE, 1 << 30, None, None) == psvt.PSVT_EINVAL
     assert lib.psvt_rank_r(FAKE, 5, 4, 4, -0.1, FAKE, 4, FAKE, 1 << 30, None, None) == psvt.PSVT_EINVAL
-    assert lib.psvt_gemm_nt(FAKE, 4, FAKE, 4, None, 0, FAKE, 4, 3, 4, 4, 1.0, 0.0, 1, None) == psvt.PSVT_EINVAL
-    assert lib.psvt_gemm_nt(ctypes.c_void_p((1 << 40) + 4), 4, FAKE, 4, None, 0, FAKE, 4, 4, 4, 4, 1.0, 0.0, 0,
+    assert lib.psvt_gemm_nt(0, FAKE, 4, FAKE, 4, None, 0, FAKE, 4, 3, 4, 4, 1.0, 0.0, 1, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_gemm_nt(0, ctypes.c_void_p((1 << 40) + 4), 4, FAKE, 4, None, 0, FAKE, 4, 4, 4, 4, 1.0, 0.0, 0,
                             None) == psvt.PSVT_EINVAL
+    assert lib.psvt_gemm_nt(1, FAKE, 4, FAKE, 8, None, 0, FAKE, 4, 4, 4, 4, 1.0, 0.0, 0, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_gemm_nt(5, FAKE, 4, FAKE, 4, None, 0, FAKE, 4, 4, 4, 4, 1.0, 0.0, 0, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_convert(1, FAKE, 4, 4, 3, FAKE, 4, 1.0, 0, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_convert(9, FAKE, 4, 4, 4, FAKE, 4, 1.0, 0, None) == psvt.PSVT_EINVAL
 
 
 def test_python_wrapper_rejects_non_2d():
@@ -114,9 +118,10 @@ def test_python_wrapper_rejects_non_2d():
 def test_tune_table_parsing(tmp_path):
     lib = psvt.load()
     good = tmp_path / "good.txt"
-    good.write_text("# comment\n1 0 0.5 10\n\n3 1 0.7 5.5  # trailing\n")
+    good.write_text("# comment\n0 1 0 0.5 10\n\n1 3 1 0.7 5.5  # trailing\n")
     assert lib.psvt_tune_load(str(good).encode()) == psvt.PSVT_OK
-    for text in ["1 0 0.5\n", "5 0 0.5 1\n", "1 2 0.5 1\n", "1 0 1.5 1\n", "1 0 0.5 -1\n", "1 0 0.5 1 extra\n"]:
+    for text in ["0 1 0 0.5\n", "0 5 0 0.5 1\n", "0 1 2 0.5 1\n", "0 1 0 1.5 1\n", "0 1 0 0.5 -1\n",
+                 "0 1 0 0.5 1 extra\n", "3 1 0 0.5 1\n"]:
         bad = tmp_path / "bad.txt"
         bad.write_text(text)
         assert lib.psvt_tune_load(str(bad).encode()) == psvt.PSVT_EINVAL, text
@@ -135,6 +140,7 @@ def test_tune_pick_model():
     assert psvt.pick_tile(4096, 4096, 4096, True) == psvt.TILE_IDS[192]
     assert psvt.pick_tile(4096, 4096, 4096, False) == psvt.TILE_IDS[256]
     assert psvt.pick_tile(512, 512, 512, True) == psvt.TILE_IDS[64]
-    assert lib.psvt_tune_pick(0, 5, 5, 0) == psvt.PSVT_EINVAL
+    assert lib.psvt_tune_pick(0, 0, 5, 5, 0) == psvt.PSVT_EINVAL
+    assert lib.psvt_tune_pick(7, 5, 5, 5, 0) == psvt.PSVT_EINVAL
     assert lib.psvt_tune_force_tile(9) == psvt.PSVT_EINVAL
-    assert lib.psvt_tune_set(1, 0, 0.0, 1.0) == psvt.PSVT_EINVAL
+    assert lib.psvt_tune_set(0, 1, 0, 0.0, 1.0) == psvt.PSVT_EINVAL

@@ -1,0 +1,173 @@
+"""GPU parity of the low-precision path: storage conversions, the BF16 and
+FP8 MFMA products, and the precision schedules of the method against the
+FP64 oracle (tolerance 1e-2, stated per result)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_22484_amd import inputs
+from tests.lowp import bf16_round, e4m3_decode, e4m3_encode
+
+pytestmark = pytest.mark.gpu
+
+TOL_LOWP = 1e-2
+
+
+def _announce(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tdev(gpu_lib):
+    import torch
+    return torch, torch.device("cuda:0")
+
+
+def dev_f32(torch, dev, A):
+    return torch.from_numpy(np.ascontiguousarray(A, dtype=np.float32)).to(dev)
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu()
+
+
+# ---------------------------------------------------------------- convert
+
+def test_convert_bf16_matches_torch(gpu_lib, tdev):
+    torch, dev = tdev
+    _announce("convert bf16")
+    rng = np.random.default_rng(3)
+    X = (rng.standard_normal((130, 77)) * np.exp(rng.uniform(-20, 20, (130, 77)))).astype(np.float32)
+    Y = host(gpu_lib.convert(dev_f32(torch, dev, X), gpu_lib.DTYPE_BF16, scale=0.5))
+    np.testing.assert_array_equal(Y.to(torch.float32).numpy(), bf16_round(0.5 * X))
+    YT = host(gpu_lib.convert(dev_f32(torch, dev, X), gpu_lib.DTYPE_BF16, scale=1.0, transpose=True))
+    np.testing.assert_array_equal(YT.to(torch.float32).numpy(), bf16_round(X).T)
+
+
+def test_convert_fp8_matches_ocp_e4m3(gpu_lib, tdev):
+    """Hardware conversion = OCP e4m3fn, round to nearest even, saturating."""
+    torch, dev = tdev
+    _announce("convert fp8")
+    rng = np.random.default_rng(4)
+    X = np.concatenate([
+        rng.uniform(-500, 500, 3000), rng.uniform(-1, 1, 3000), rng.uniform(-2.0 ** -6, 2.0 ** -6, 2000),
+        np.array([0.0, -0.0, 448.0, -448.0, 449.0, 1e6, -1e6, 1.0625, 1.1875, 2.0 ** -10, 3 * 2.0 ** -10]),
+    ]).astype(np.float32)
+    X = np.pad(X, (0, (-len(X)) % 64)).reshape(-1, 64)
+    codes = host(gpu_lib.convert(dev_f32(torch, dev, X), gpu_lib.DTYPE_FP8, scale=1.0)).numpy()
+    ref = e4m3_encode(X.astype(np.float64))
+    # +0 and -0 may differ only in the sign bit of a zero
+    got_v, ref_v = e4m3_decode(codes), e4m3_decode(ref)
+    np.testing.assert_array_equal(got_v, ref_v)
+
+
+# ------------------------------------------------------------------ GEMMs
+
+def quantize(torch, dev, A, dtype, scale):
+    """Host-side quantisation; returns (device operand, dequantised float64)."""
+    if dtype == 1:
+        q = bf16_round(scale * A)
+        return torch.from_numpy(q).to(torch.bfloat16).to(dev), q.astype(np.float64) / scale
+    codes = e4m3_encode(scale * A.astype(np.float64))
+    return torch.from_numpy(codes).to(dev), e4m3_decode(codes) / scale
+
+
+@pytest.mark.parametrize("dtype", [1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("M,N,K,sym", [(200, 136, 256, False), (250, 250, 192, True), (64, 70, 100, False)])
+def test_lowp_gemm_matches_fp64(gpu_lib, tdev, dtype, tile, M, N, K, sym):
+    torch, dev = tdev
+    _announce("lowp gemm dtype=%d tile=%d %dx%dx%d sym=%s" % (dtype, tile, M, N, K, sym))
+    rng = np.random.default_rng([M, N, K, dtype, tile])
+    Kp = (K + 15) // 16 * 16
+    A = np.zeros((M, Kp), np.float32)
+    A[:, :K] = rng.standard_normal((M, K))
+    B = A if sym else np.pad(rng.standard_normal((N, K)).astype(np.float32), ((0, 0), (0, Kp - K)))
+    scale = 16.0 if dtype == 2 else 1.0
+    Aq, A64 = quantize(torch, dev, A, dtype, scale)
+    Bq, B64 = (Aq, A64) if sym else quantize(torch, dev, B, dtype, scale)
+    Cbuf = torch.zeros((M, (N + 3) // 4 * 4), device=dev)
+    gpu_lib.force_tile(tile)
+    try:
+        # the kernel multiplies the raw product by alpha: undo the scales
+        C = gpu_lib.gemm_nt(Aq, Bq, alpha=1.0 / (scale * scale), sym=sym,
+                            out=Cbuf[:, :N], dtype=dtype)
+        got = host(C).numpy().astype(np.float64)
+    finally:
+        gpu_lib.force_tile(0)
+    ref = A64 @ B64.T
+    bound = (np.abs(A64) @ np.abs(B64).T) * (Kp + 2) * 2.0 ** -24
+    assert np.all(np.abs(got - ref) <= bound + 1e-30), np.max(np.abs(got - ref) - bound)
+
+
+# ------------------------------------------------------ precision schedules
+
+def _noisy(m, n, r=40, idx=0):
+    return inputs.noisy_lowrank(m, n, rank=r, idx=idx, cfg=inputs.CFG_TEST)
+
+
+@pytest.mark.parametrize("shape", [(768, 384), (384, 768)])
+def test_bf16_schedule_svt(gpu_lib, tdev, shape):
+    """18 BF16 + 2 FP32 iterations on low-rank signal + noise (the
+    precision-form recipe at a size the oracle finishes in seconds)."""
+    torch, dev = tdev
+    m, n = shape
+    pb = _noisy(m, n)
+    _announce("svt bf16 %s tau=%.4g" % (shape, pb.tau))
+    Y = host(gpu_lib.svt(dev_f32(torch, dev, pb.A), pb.tau, iters=20, n_bf16=18)).numpy().astype(np.float64)
+    ref = oracle.svt(pb.A, pb.tau)
+    err = oracle.rel_fro_err(Y, ref)
+    print("bf16 %s rel err %.3e" % (shape, err))
+    assert err <= TOL_LOWP
+
+
+@pytest.mark.parametrize("shape", [(768, 384), (512, 512)])
+def test_fp8_bf16_schedule_svt(gpu_lib, tdev, shape):
+    """6 FP8 + 12 BF16 + 2 FP32 iterations (the serving schedule)."""
+    torch, dev = tdev
+    m, n = shape
+    pb = _noisy(m, n, r=32, idx=1)
+    _announce("svt fp8 %s tau=%.4g" % (shape, pb.tau))
+    Y = host(gpu_lib.svt(dev_f32(torch, dev, pb.A), pb.tau, iters=20, n_fp8=6, n_bf16=12)).numpy()
+    ref = oracle.svt(pb.A, pb.tau)
+    err = oracle.rel_fro_err(Y.astype(np.float64), ref)
+    print("fp8 %s rel err %.3e" % (shape, err))
+    assert err <= TOL_LOWP
+
+
+def test_bf16_constructed_spectrum(gpu_lib, tdev):
+    torch, dev = tdev
+    pb = inputs.square_case(0.5, n=384, m=512)
+    _announce("svt bf16 constructed")
+    Y = host(gpu_lib.svt(dev_f32(torch, dev, pb.A), pb.tau, iters=20, n_bf16=18)).numpy().astype(np.float64)
+    err = oracle.rel_fro_err(Y, oracle.svt(pb.A, pb.tau))
+    print("bf16 constructed rel err %.3e" % err)
+    assert err <= TOL_LOWP
+
+
+@pytest.mark.parametrize("n_fp8,n_bf16", [(0, 18), (6, 12)])
+def test_lowp_polar_and_sign(gpu_lib, tdev, n_fp8, n_bf16):
+    torch, dev = tdev
+    _announce("polar/sign lowp %d %d" % (n_fp8, n_bf16))
+    pb = inputs.constructed(inputs.CFG_TEST, 77, 400, 256, inputs.log_spectrum(256, 1.0, 1e-2), 0.0)
+    P = host(gpu_lib.polar(dev_f32(torch, dev, pb.A), iters=20, n_fp8=n_fp8, n_bf16=n_bf16)).numpy()
+    assert oracle.rel_fro_err(P.astype(np.float64), oracle.polar(pb.A)) <= TOL_LOWP
+    rng = inputs.rng_for(inputs.CFG_TEST, 901)
+    Q = inputs.haar_columns(rng, 200, 200)
+    lam = inputs.log_spectrum(200, 1.0, 1e-2) * np.where(np.arange(200) % 2 == 0, -1.0, 1.0)
+    G = ((Q * lam) @ Q.T).astype(np.float32)
+    S = host(gpu_lib.polar_sym(dev_f32(torch, dev, G), iters=20, n_fp8=n_fp8, n_bf16=n_bf16)).numpy()
+    assert oracle.rel_fro_err(S.astype(np.float64), oracle.polar_sym(G)) <= TOL_LOWP
+
+
+def test_lowp_rank_r(gpu_lib, tdev):
+    torch, dev = tdev
+    pb = inputs.rank_case(r=32, n=320, m=480)
+    _announce("rank_r bf16")
+    Y = host(gpu_lib.rank_r(dev_f32(torch, dev, pb.A), pb.tau, iters=20, n_bf16=18)).numpy()
+    assert oracle.rel_fro_err(Y.astype(np.float64), oracle.rank_r(pb.A, pb.tau)) <= TOL_LOWP
