@@ -56,6 +56,21 @@ enum {
 /* operation ids for psvt_workspace_bytes */
 enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R = 3 };
 
+/* psvt_config.flags.  The sign iteration S works on A^T A - tau^2 I, whose
+ * spectrum is the square of A's, so the eigenvalues that decide the sign
+ * are far below bfloat16 resolution of the largest one.  By default its
+ * low-precision iterations therefore use "split bf16" operands (x = hi + lo,
+ * two bf16 planes, products hi.hi + hi.lo + lo.hi: three bf16 MFMA passes,
+ * about 16 mantissa bits).
+ *   PSVT_FLAG_PLAIN_S  S's low-precision iterations use plain FP8/BF16
+ *                      operands (faster, loses the small eigenvalues).
+ *   PSVT_FLAG_SPLIT_P  P's BF16 iterations use split bf16 as well (needed
+ *                      when tau is close to the retained singular values:
+ *                      the error of P enters A_tau multiplied by
+ *                      tau / (sigma - tau)). */
+#define PSVT_FLAG_PLAIN_S 0x1u
+#define PSVT_FLAG_SPLIT_P 0x2u
+
 /* side selection (Proposition 1 and its footnote) */
 enum { PSVT_SIDE_AUTO = 0, PSVT_SIDE_RIGHT = 1, PSVT_SIDE_LEFT = 2 };
 
@@ -76,7 +91,8 @@ typedef struct psvt_config {
      * replaces the built-in schedule (the paper's listing lets the caller
      * inject the polar algorithm).  Read during the call only. */
     const double *coeffs;
-    uint32_t flags; /* reserved, must be 0 */
+    /* PSVT_FLAG_* bits; 0 = defaults. */
+    uint32_t flags;
     int32_t reserved[3];
 } psvt_config;
 
@@ -112,7 +128,9 @@ int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, f
  * psvt_gemm_nt: the MFMA product used by every step of the method,
  *     C[i][j] = alpha * sum_k A[i][k] B[j][k] + beta * D[i][j]
  * with A (M x K) and B (N x K) stored in `dtype` (PSVT_DTYPE_F32: float,
- * PSVT_DTYPE_BF16: bfloat16 bits, PSVT_DTYPE_FP8: OCP e4m3 bytes) and C, D
+ * PSVT_DTYPE_BF16: bfloat16 bits, PSVT_DTYPE_FP8: OCP e4m3 bytes,
+ * PSVT_DTYPE_BF16X3: split bfloat16, the hi plane followed by the lo plane,
+ * each rows x ld, product hi.hi + hi.lo + lo.hi) and C, D
  * (M x N) float32; all row-major device buffers, 16-byte aligned, with every
  * row stride a multiple of 16 bytes.  Products accumulate in FP32.  D may be
  * NULL.  sym != 0 requires M == N and computes only the lower block
@@ -120,7 +138,8 @@ int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, f
  * symmetric, e.g. A = B).
  *
  * psvt_convert: Y = round(scale * X) into `dtype` (bfloat16: round to
- * nearest even; FP8 e4m3: round to nearest even, saturated to +-448), or
+ * nearest even; FP8 e4m3: round to nearest even, saturated to +-448; split
+ * bfloat16: hi = bf16(x) then lo = bf16(x - hi) in a second plane), or
  * into float32 when dtype is PSVT_DTYPE_F32; transpose != 0 writes
  * Y[j][i] instead of Y[i][j].  X: rows x cols float32 (ldx), Y: ldy in
  * elements of `dtype`. */
@@ -168,7 +187,7 @@ int psvt_trace_end(psvt_trace_stat *out, int max_entries, int *n_entries);
  *   psvt_tune_pick             the id the model picks for an M x N x K
  *                              product (>= 1), or a negative error code.
  * The model is process-wide; change it before concurrent calls. */
-enum { PSVT_DTYPE_F32 = 0, PSVT_DTYPE_BF16 = 1, PSVT_DTYPE_FP8 = 2 };
+enum { PSVT_DTYPE_F32 = 0, PSVT_DTYPE_BF16 = 1, PSVT_DTYPE_FP8 = 2, PSVT_DTYPE_BF16X3 = 3 };
 int psvt_tune_force_tile(int tile);
 int psvt_tune_set(int dtype, int tile, int sym, double efficiency, double overhead_us);
 int psvt_tune_load(const char *path);

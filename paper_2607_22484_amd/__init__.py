@@ -25,7 +25,8 @@ PSVT_EHIP = -4
 
 OP_SVT, OP_POLAR, OP_POLAR_SYM, OP_RANK_R = 0, 1, 2, 3
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
-DTYPE_F32, DTYPE_BF16, DTYPE_FP8 = 0, 1, 2
+DTYPE_F32, DTYPE_BF16, DTYPE_FP8, DTYPE_BF16X3 = 0, 1, 2, 3
+FLAG_PLAIN_S, FLAG_SPLIT_P = 0x1, 0x2
 
 EXPORTED = [
     "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
@@ -114,8 +115,9 @@ def _check(rc: int, where: str):
 
 
 def make_config(iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
-                coeffs: Optional[Sequence[float]] = None):
+                coeffs: Optional[Sequence[float]] = None, flags: int = 0):
     cfg = Config()
+    cfg.flags = int(flags)
     cfg.iters = int(iters)
     cfg.n_fp8 = int(n_fp8)
     cfg.n_bf16 = int(n_bf16)
@@ -188,12 +190,12 @@ def _ld_any(A):
 
 
 def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
-        coeffs=None, out=None, ws=None):
+        coeffs=None, out=None, ws=None, flags: int = 0):
     """A_tau = U max(Sigma - tau I, 0) V^T via Proposition 1 (FP32 out)."""
     _check_input(A)
     torch = _torch()
     m, n = A.shape
-    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs)
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs, flags)
     Y = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
     if m == 0 or n == 0:
         return Y
@@ -206,12 +208,12 @@ def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: i
 
 
 def rank_r(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
-           coeffs=None, out=None, ws=None):
+        coeffs=None, out=None, ws=None, flags: int = 0):
     """Best rank-r approximation (Corollary 1), tau between sigma_{r+1} and sigma_r."""
     _check_input(A)
     torch = _torch()
     m, n = A.shape
-    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs)
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs, flags)
     Y = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
     if m == 0 or n == 0:
         return Y
@@ -224,12 +226,12 @@ def rank_r(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side
 
 
 def polar(A, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO, coeffs=None, out=None,
-          ws=None):
+          ws=None, flags: int = 0):
     """Polar factor U V^T (section 2)."""
     _check_input(A)
     torch = _torch()
     m, n = A.shape
-    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs)
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs, flags)
     P = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
     if m == 0 or n == 0:
         return P
@@ -241,14 +243,15 @@ def polar(A, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_
     return P
 
 
-def polar_sym(G, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, coeffs=None, out=None, ws=None):
+def polar_sym(G, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, coeffs=None, out=None, ws=None,
+              flags: int = 0):
     """Matrix sign of symmetric G (symmetrised on load)."""
     _check_input(G, "G")
     torch = _torch()
     n, n2 = G.shape
     if n != n2:
         raise ValueError("polar_sym needs a square matrix")
-    cfg, keep = make_config(iters, n_fp8, n_bf16, SIDE_AUTO, coeffs)
+    cfg, keep = make_config(iters, n_fp8, n_bf16, SIDE_AUTO, coeffs, flags)
     S = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=G.device)
     if n == 0:
         return S
@@ -293,7 +296,10 @@ def convert(X, dtype: int, scale: float = 1.0, transpose: bool = False, out=None
     _check_input(X, "X")
     rows, cols = X.shape
     shape = (cols, rows) if transpose else (rows, cols)
-    tdt = {DTYPE_F32: torch.float32, DTYPE_BF16: torch.bfloat16, DTYPE_FP8: torch.uint8}[dtype]
+    tdt = {DTYPE_F32: torch.float32, DTYPE_BF16: torch.bfloat16, DTYPE_FP8: torch.uint8,
+           DTYPE_BF16X3: torch.bfloat16}[dtype]
+    if dtype == DTYPE_BF16X3:  # hi plane then lo plane
+        shape = (2 * shape[0], shape[1])
     Y = out if out is not None else torch.empty(shape, dtype=tdt, device=X.device)
     with torch.cuda.device(X.device):
         _check(load().psvt_convert(int(dtype), X.data_ptr(), rows, cols, _ld(X), Y.data_ptr(), _ld_any(Y),

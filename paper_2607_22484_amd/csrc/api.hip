@@ -91,6 +91,7 @@ struct Cfg {
     int n_fp8, n_bf16;
     int side;
     const double *coeffs;
+    uint32_t flags;
 };
 
 int read_cfg(const psvt_config *c, Cfg &out) {
@@ -98,6 +99,7 @@ int read_cfg(const psvt_config *c, Cfg &out) {
     out.n_fp8 = out.n_bf16 = 0;
     out.side = PSVT_SIDE_AUTO;
     out.coeffs = nullptr;
+    out.flags = 0;
     if (!c) return PSVT_OK;
     if (c->iters < 0 || c->iters > 256) return fail(PSVT_EINVAL, "iters = %d outside 0..256", c->iters);
     if (c->iters) out.iters = c->iters;
@@ -105,7 +107,9 @@ int read_cfg(const psvt_config *c, Cfg &out) {
         return fail(PSVT_EINVAL, "n_fp8 = %d, n_bf16 = %d do not fit in %d iterations", c->n_fp8, c->n_bf16,
                     out.iters);
     if (c->side < 0 || c->side > 2) return fail(PSVT_EINVAL, "side = %d", c->side);
-    if (c->flags != 0) return fail(PSVT_EINVAL, "flags must be 0");
+    if (c->flags & ~(uint32_t)(PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S))
+        return fail(PSVT_EINVAL, "unknown flags 0x%x", c->flags);
+    out.flags = c->flags;
     out.n_fp8 = c->n_fp8;
     out.n_bf16 = c->n_bf16;
     out.side = c->side;
@@ -129,6 +133,23 @@ int iter_dtype(const Cfg &c, int t) {
     if (t < c.n_fp8) return OP_FP8;
     if (t < c.n_fp8 + c.n_bf16) return OP_BF16;
     return OP_F32;
+}
+
+// P iterations: as scheduled, BF16 as split bf16 when PSVT_FLAG_SPLIT_P.
+int iter_dtype_P(const Cfg &c, int t) {
+    const int d = iter_dtype(c, t);
+    return (d == OP_BF16 && (c.flags & PSVT_FLAG_SPLIT_P)) ? OP_BF16X3 : d;
+}
+
+// S iterations work on the shifted Gram, whose spectrum is the square of A's:
+// the eigenvalues that decide the sign sit far below bf16 resolution of the
+// largest one (sigma_min^2 - tau^2 vs sigma_max^2).  Their low-precision
+// iterations therefore use split bf16 (about 16 mantissa bits) unless
+// PSVT_FLAG_PLAIN_S asks for plain operands.
+int iter_dtype_S(const Cfg &c, int t) {
+    const int d = iter_dtype(c, t);
+    if (d == OP_F32 || (c.flags & PSVT_FLAG_PLAIN_S)) return d;
+    return OP_BF16X3;
 }
 
 // FP8 operand scales of one iteration: the copies of X (and X^T), of T = X^T X
@@ -157,7 +178,7 @@ void iteration_scales(const Cfg &c, IterScale *out) {
         double beta = 0.0, unext = 0.0;
         const int n = 4096;
         for (int k = 0; k <= n; ++k) {
-            const double x = 1.05 * U * k / n, mu = x * x;
+            const double x = U * k / n, mu = x * x;
             beta = fmax(beta, fabs(b * mu + cc * mu * mu));
             unext = fmax(unext, fabs(x * (a + b * mu + cc * mu * mu)));
         }
@@ -177,9 +198,11 @@ struct Layout {
     size_t X0 = 0, X0T = 0, Xp = 0, Xq = 0, XTp = 0, XTq = 0;
     size_t T = 0, Bm = 0;
     size_t H = 0, R = 0, S0 = 0, S1 = 0, X2 = 0, BS = 0;
-    // low-precision operand copies (2 bytes per element of room)
+    // low-precision operand copies: room for two bf16 planes per element
+    // (split bf16); plane strides in elements
     bool lp = false;
     size_t XL[2] = {0, 0}, XTL[2] = {0, 0}, TL = 0, BL = 0, SL[2] = {0, 0};
+    int64_t planeX = 0, planeXT = 0, planeS = 0;
     size_t total = 0;
 };
 
@@ -242,15 +265,18 @@ Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c) {
     }
     L.lp = c.n_fp8 + c.n_bf16 > 0;
     if (L.lp) {
-        L.TL = take(fS / 2);
-        L.BL = take(fS / 2);
+        L.TL = take(fS);
+        L.BL = take(fS);
         if (need_P)
             for (int i = 0; i < 2; ++i) {
-                L.XL[i] = take(fX / 2);
-                L.XTL[i] = take(fXT / 2);
+                L.XL[i] = take(fX);
+                L.XTL[i] = take(fXT);
             }
         if (need_S)
-            for (int i = 0; i < 2; ++i) L.SL[i] = take(fS / 2);
+            for (int i = 0; i < 2; ++i) L.SL[i] = take(fS);
+        L.planeX = L.l * L.ldS;
+        L.planeXT = L.s * L.ldL;
+        L.planeS = L.s * L.ldS;
     }
     L.total = off;
     return L;
@@ -352,7 +378,10 @@ void set_operand_scales(GemmArgs &g, int dt, float sa, float sb) {
 }
 
 // Low-precision copies that a product writes for the next consumer.
-void set_lp_out(GemmArgs &g, int type, void *row, int64_t ldrow, void *trans, int64_t ldtrans, float scale) {
+void set_lp_out(GemmArgs &g, int type, void *row, int64_t ldrow, void *trans, int64_t ldtrans, float scale,
+                int64_t plane, int64_t plane_t = 0) {
+    g.lp_plane = plane;
+    g.lp_plane_t = plane_t;
     g.lp_type = type;
     g.Clp = row;
     g.ldclp = ldrow;
@@ -387,20 +416,21 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
         float a, b, cc;
         coef(c, t, a, b, cc);
         const bool first = t == 0, last = t == c.iters - 1;
-        const int dt = iter_dtype(c, t), nd = last ? OP_F32 : iter_dtype(c, t + 1);
+        const int dt = iter_dtype_P(c, t), nd = last ? OP_F32 : iter_dtype_P(c, t + 1);
         const bool lp = dt != OP_F32;
         const float sX = dt == OP_FP8 ? scl[t].sX : 1.0f, sT = dt == OP_FP8 ? scl[t].sT : 1.0f,
                     sB = dt == OP_FP8 ? scl[t].sB : 1.0f, sXn = nd == OP_FP8 ? scl[t + 1].sX : 1.0f;
         if (first && lp) {
             // theta is folded into the first copies: X0 / theta and T / theta^2
-            HIP_TRY(launch_convert(curX, L.l, L.s, L.ldS, bufXlp[1], L.ldS, dt, sX, 0, st, sc, F_P1), "P: X0 copy");
-            HIP_TRY(launch_convert(T, L.s, L.s, L.ldS, Tlp, L.ldS, dt, sT, 0, st, sc, F_P2), "P: T copy");
+            HIP_TRY(launch_convert(curX, L.l, L.s, L.ldS, bufXlp[1], L.ldS, dt, sX, 0, st, sc, F_P1, L.planeX), "P: X0 copy");
+            HIP_TRY(launch_convert(T, L.s, L.s, L.ldS, Tlp, L.ldS, dt, sT, 0, st, sc, F_P2, L.planeS), "P: T copy");
             curXlp = bufXlp[1];
         }
         if (!first) {  // T = X^T X
             GemmArgs g = gemm_defaults();
             g.A = g.B = lp ? curXTlp : (const void *)curXT;
             g.lda = g.ldb = L.ldL;
+            g.a_plane = g.b_plane = L.planeXT;
             g.C = T;
             g.ldc = L.ldS;
             g.M = g.N = (int)L.s;
@@ -408,13 +438,14 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
             g.sc = sc;
             g.sym = 1;
             set_operand_scales(g, dt, sX, sX);
-            if (lp) set_lp_out(g, dt, Tlp, L.ldS, nullptr, 0, sT);
+            if (lp) set_lp_out(g, dt, Tlp, L.ldS, nullptr, 0, sT, L.planeS);
             HIP_TRY(launch_gemm(g, dt, st), "P: X^T X");
         }
         {  // B = c T^2 + b T   (first iteration: theta scaling through device scalars)
             GemmArgs g = gemm_defaults();
             g.A = g.B = lp ? Tlp : (const void *)T;
             g.lda = g.ldb = L.ldS;
+            g.a_plane = g.b_plane = L.planeS;
             g.D = T;
             g.ldd = L.ldS;
             g.M = g.N = g.K = (int)L.s;
@@ -426,7 +457,7 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
             g.sym = 1;
             set_operand_scales(g, dt, sT, sT);
             if (lp) {
-                set_lp_out(g, dt, Blp, L.ldS, nullptr, 0, sB);
+                set_lp_out(g, dt, Blp, L.ldS, nullptr, 0, sB, L.planeS);
             } else {
                 g.C = Bm;
                 g.ldc = L.ldS;
@@ -439,6 +470,8 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
             g.lda = L.ldS;
             g.B = lp ? (const void *)Blp : (const void *)Bm;
             g.ldb = L.ldS;
+            g.a_plane = L.planeX;
+            g.b_plane = L.planeS;
             g.D = curX;
             g.ldd = L.ldS;
             g.M = (int)L.l;
@@ -467,7 +500,7 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
                         g.CT = bufXT[k];
                         g.ldct = L.ldL;
                     } else {
-                        set_lp_out(g, nd, bufXlp[k], L.ldS, bufXTlp[k], L.ldL, sXn);
+                        set_lp_out(g, nd, bufXlp[k], L.ldS, bufXTlp[k], L.ldL, sXn, L.planeX, L.planeXT);
                     }
                 }
             }
@@ -501,13 +534,13 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
         float a, b, cc;
         coef(c, t, a, b, cc);
         const bool first = t == 0, last = t == c.iters - 1;
-        const int dt = iter_dtype(c, t), nd = last ? OP_F32 : iter_dtype(c, t + 1);
+        const int dt = iter_dtype_S(c, t), nd = last ? OP_F32 : iter_dtype_S(c, t + 1);
         const bool lp = dt != OP_F32;
         const float sX = dt == OP_FP8 ? scl[t].sX : 1.0f, sT = dt == OP_FP8 ? scl[t].sT : 1.0f,
                     sB = dt == OP_FP8 ? scl[t].sB : 1.0f, sXn = nd == OP_FP8 ? scl[t + 1].sX : 1.0f;
         if (first && lp) {
-            HIP_TRY(launch_convert(cur, s, s, ld, buflp[1], ld, dt, sX, 0, st, sc, F_S1), "S: H copy");
-            HIP_TRY(launch_convert(R, s, s, ld, X2lp, ld, dt, sT, 0, st, sc, F_S2), "S: H^2 copy");
+            HIP_TRY(launch_convert(cur, s, s, ld, buflp[1], ld, dt, sX, 0, st, sc, F_S1, L.planeS), "S: H copy");
+            HIP_TRY(launch_convert(R, s, s, ld, X2lp, ld, dt, sT, 0, st, sc, F_S2, L.planeS), "S: H^2 copy");
             curlp = buflp[1];
         }
         const float *sq = R;
@@ -515,13 +548,14 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
             GemmArgs g = gemm_defaults();
             g.A = g.B = lp ? curlp : (const void *)cur;
             g.lda = g.ldb = ld;
+            g.a_plane = g.b_plane = L.planeS;
             g.C = X2;
             g.ldc = ld;
             g.M = g.N = g.K = (int)s;
             g.sc = sc;
             g.sym = 1;
             set_operand_scales(g, dt, sX, sX);
-            if (lp) set_lp_out(g, dt, X2lp, ld, nullptr, 0, sT);
+            if (lp) set_lp_out(g, dt, X2lp, ld, nullptr, 0, sT, L.planeS);
             HIP_TRY(launch_gemm(g, dt, st), "S: X^2");
             sq = X2;
         }
@@ -529,6 +563,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
             GemmArgs g = gemm_defaults();
             g.A = g.B = lp ? (const void *)X2lp : (const void *)sq;
             g.lda = g.ldb = ld;
+            g.a_plane = g.b_plane = L.planeS;
             g.D = sq;
             g.ldd = ld;
             g.M = g.N = g.K = (int)s;
@@ -540,7 +575,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
             g.sym = 1;
             set_operand_scales(g, dt, sT, sT);
             if (lp) {
-                set_lp_out(g, dt, BSlp, ld, nullptr, 0, sB);
+                set_lp_out(g, dt, BSlp, ld, nullptr, 0, sB, L.planeS);
             } else {
                 g.C = BS;
                 g.ldc = ld;
@@ -558,6 +593,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
             g.A = lp ? (const void *)BSlp : (const void *)BS;
             g.B = lp ? curlp : (const void *)cur;
             g.lda = g.ldb = ld;
+            g.a_plane = g.b_plane = L.planeS;
             g.D = cur;
             g.ldd = ld;
             g.M = g.N = g.K = (int)s;
@@ -573,7 +609,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
             float *dst = (last && user_out) ? user_out : buf[k];
             g.C = dst;
             g.ldc = (last && user_out) ? ld_out : ld;
-            if (!last && nd != OP_F32) set_lp_out(g, nd, buflp[k], ld, nullptr, 0, sXn);
+            if (!last && nd != OP_F32) set_lp_out(g, nd, buflp[k], ld, nullptr, 0, sXn, L.planeS);
             HIP_TRY(launch_gemm(g, dt, st), "S: a X + B X");
             cur = dst;
             curlp = buflp[k];
@@ -740,7 +776,7 @@ int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t l
                  float *C, int64_t ldc, int64_t M, int64_t N, int64_t K, float alpha, float beta, int sym,
                  void *stream) {
     g_last_error.clear();
-    if (dtype < 0 || dtype > 2) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
+    if (dtype < 0 || dtype > 3) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
     if (M < 0 || N < 0 || K < 0) return fail(PSVT_EINVAL, "negative size");
     if (M == 0 || N == 0) return PSVT_OK;
     if (M > (1LL << 30) || N > (1LL << 30) || K > (1LL << 30)) return fail(PSVT_EINVAL, "size too large");
@@ -748,7 +784,7 @@ int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t l
     if (K > 0 && (!A || !B)) return fail(PSVT_EINVAL, "A or B is NULL");
     if (ldc < N || (K > 0 && (lda < K || ldb < K)) || (D && ldd < N)) return fail(PSVT_EINVAL, "bad leading dimension");
     if (sym && M != N) return fail(PSVT_EINVAL, "sym needs M == N");
-    const int esz = dtype == PSVT_DTYPE_F32 ? 4 : (dtype == PSVT_DTYPE_BF16 ? 2 : 1);
+    const int esz = dtype == PSVT_DTYPE_F32 ? 4 : (dtype == PSVT_DTYPE_FP8 ? 1 : 2);
     auto al16 = [](const void *p, int64_t ldbytes) { return p == nullptr || (((uintptr_t)p & 15) == 0 && ldbytes % 16 == 0); };
     if (!al16(A, lda * esz) || !al16(B, ldb * esz) || !al16(C, ldc * 4) || !al16(D, ldd * 4))
         return fail(PSVT_EINVAL, "operands must be 16-byte aligned with 16-byte-multiple row strides");
@@ -769,6 +805,8 @@ int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t l
     g.alpha = alpha;
     g.beta = beta;
     g.sym = sym ? 1 : 0;
+    g.a_plane = M * lda;  // split bf16: the lo plane follows the hi plane
+    g.b_plane = N * ldb;
     HIP_TRY(launch_gemm(g, dtype, (hipStream_t)stream), "gemm");
     return PSVT_OK;
 }
@@ -776,7 +814,7 @@ int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t l
 int psvt_convert(int dtype, const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y, int64_t ldy,
                  float scale, int transpose, void *stream) {
     g_last_error.clear();
-    if (dtype < 0 || dtype > 2) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
+    if (dtype < 0 || dtype > 3) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
     if (rows < 0 || cols < 0) return fail(PSVT_EINVAL, "negative size");
     if (rows == 0 || cols == 0) return PSVT_OK;
     if (!X || !Y) return fail(PSVT_EINVAL, "NULL buffer");
@@ -784,7 +822,9 @@ int psvt_convert(int dtype, const float *X, int64_t rows, int64_t cols, int64_t 
     if (!isfinite(scale)) return fail(PSVT_EINVAL, "scale must be finite");
     int rc = check_device();
     if (rc) return rc;
-    HIP_TRY(launch_convert(X, rows, cols, ldx, Y, ldy, dtype, scale, transpose ? 1 : 0, (hipStream_t)stream),
+    const int64_t plane = (transpose ? cols : rows) * ldy;  // split bf16: lo plane after the hi plane
+    HIP_TRY(launch_convert(X, rows, cols, ldx, Y, ldy, dtype, scale, transpose ? 1 : 0, (hipStream_t)stream, nullptr,
+                           -1, plane),
             "convert");
     return PSVT_OK;
 }

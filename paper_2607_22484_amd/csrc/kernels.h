@@ -31,8 +31,11 @@ struct Scalars {
     float f[F_COUNT];
 };
 
-// Element types of the GEMM operands.
-enum OpType { OP_F32 = 0, OP_BF16 = 1, OP_FP8 = 2 };
+// Element types of the GEMM operands.  OP_BF16X3 ("split bfloat16") stores
+// x = hi + lo as two bf16 planes (hi = bf16(x), lo = bf16(x - hi)); a product
+// of two split operands is hi.hi + hi.lo + lo.hi (three bf16 MFMA passes,
+// about 16 mantissa bits).
+enum OpType { OP_F32 = 0, OP_BF16 = 1, OP_FP8 = 2, OP_BF16X3 = 3 };
 
 // One NT product with a fused prologue and epilogue:
 //   W[i][k]  = wa * A[i][k] (+ wa2 * A2[i][k])               (prologue)
@@ -61,6 +64,8 @@ struct GemmArgs {
     int c_vec;       // C may take 16-byte stores (aligned, ldc % 4 == 0)
     int ct_vec;      // CT may take 16-byte stores
     int lp_type;     // OpType of Clp/CTlp
+    int64_t a_plane, b_plane;  // OP_BF16X3 operands: elements from the hi to the lo plane
+    int64_t lp_plane, lp_plane_t;  // OP_BF16X3 copies Clp / CTlp: elements from the hi to the lo plane
 };
 
 // Launchers (enqueue only).  Return a hipError_t.
@@ -76,7 +81,7 @@ hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float
 // Y = round(scale * [sc->f[i_scale]] * X) in op_type, optionally transposed.
 hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy,
                           int op_type, float scale, int transpose, hipStream_t st, const Scalars *sc = nullptr,
-                          int i_scale = -1);
+                          int i_scale = -1, int64_t plane = 0);
 
 // modes for launch_fro_norm
 enum NormMode {

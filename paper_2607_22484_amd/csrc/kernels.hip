@@ -98,6 +98,11 @@ struct Op<OP_BF16> {
     static constexpr int EPC = 8;
 };
 template <>
+struct Op<OP_BF16X3> {
+    typedef uint16_t T;
+    static constexpr int EPC = 8;
+};
+template <>
 struct Op<OP_FP8> {
     typedef uint8_t T;
     static constexpr int EPC = 16;
@@ -121,11 +126,19 @@ __device__ __forceinline__ uint8_t to_fp8(float x) {
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF);
 }
 
-__device__ __forceinline__ void store_lp(void *base, int type, int64_t idx, float v) {
-    if (type == OP_BF16)
+// Store one value in a low-precision copy; split bf16 writes hi at idx and
+// the residual lo at idx + plane.
+__device__ __forceinline__ void store_lp(void *base, int type, int64_t idx, float v, int64_t plane = 0) {
+    if (type == OP_BF16) {
         ((uint16_t *)base)[idx] = to_bf16(v);
-    else
+    } else if (type == OP_BF16X3) {
+        const uint16_t hi = to_bf16(v);
+        const float hv = __uint_as_float((uint32_t)hi << 16);
+        ((uint16_t *)base)[idx] = hi;
+        ((uint16_t *)base)[idx + plane] = to_bf16(v - hv);
+    } else {
         ((uint8_t *)base)[idx] = to_fp8(v);
+    }
 }
 
 // One MFMA step pair over 32 bytes of k per lane (two 16-byte chunks).
@@ -139,7 +152,7 @@ __device__ __forceinline__ floatx16 mfma_32b(const u32x4 &a0, const u32x4 &a1, c
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a1[e]), __uint_as_float(b1[e]), acc, 0, 0, 0);
-    } else if constexpr (ET == OP_BF16) {
+    } else if constexpr (ET == OP_BF16 || ET == OP_BF16X3) {
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0),
                                                       acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a1), __builtin_bit_cast(bf16x8, b1),
@@ -175,7 +188,7 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j,
         if (!wr[e]) continue;
         const int64_t i = ib + e;
         if (g.C) g.C[i * g.ldc + j] = v[e];
-        if (g.Clp) store_lp(g.Clp, g.lp_type, i * g.ldclp + j, v[e] * g.lp_scale);
+        if (g.Clp) store_lp(g.Clp, g.lp_type, i * g.ldclp + j, v[e] * g.lp_scale, g.lp_plane);
     }
     float *ct = SYM ? g.C : g.CT;
     const int64_t ldct = SYM ? g.ldc : g.ldct;
@@ -198,7 +211,7 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j,
     if (ctl) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (t[e]) store_lp(ctl, g.lp_type, (int64_t)j * ldctl + ib + e, v[e] * g.lp_scale);
+            if (t[e]) store_lp(ctl, g.lp_type, (int64_t)j * ldctl + ib + e, v[e] * g.lp_scale, SYM ? g.lp_plane : g.lp_plane_t);
     }
 }
 
@@ -247,7 +260,11 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
     }
 
     const int lrow = tid >> 3, lchunk = tid & 7;
-    u32x4 ra[RA], rb[RB];
+    // two register sets: tile k+2 is loaded while tile k is multiplied and
+    // tile k+1 waits to be written to LDS (two k-tiles of latency cover)
+    // (one set for the largest tiles, where two would not fit in registers)
+    constexpr int DEPTH = (BM >= 192) ? 1 : 2;
+    u32x4 ra[DEPTH][RA], rb[DEPTH][RB];
 
     auto load_chunk = [&](const T *P, int64_t ld, int row, int rows, int k) -> u32x4 {
         u32x4 v = {0u, 0u, 0u, 0u};
@@ -273,11 +290,22 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
         }
         return v;
     };
-    auto gload = [&](int k0) {
+    // Split bf16: the k loop runs over three virtual segments of Kp = K
+    // rounded up to a k-tile; A reads planes (hi, hi, lo), B (hi, lo, hi).
+    constexpr bool SPLIT = ET == OP_BF16X3;
+    const int Kp = SPLIT ? ((g.K + BK - 1) / BK) * BK : g.K;
+    auto gload = [&](int kv, auto set) {
+        int k0 = kv, seg = 0;
+        if constexpr (SPLIT) {
+            seg = kv / Kp;
+            k0 = kv - seg * Kp;
+        }
+        const T *Ap = SPLIT && seg == 2 ? A + g.a_plane : A;
+        const T *Bp = SPLIT && seg == 1 ? B + g.b_plane : B;
 #pragma unroll
         for (int p = 0; p < RA; ++p) {
             const int r = lrow + 32 * p;
-            u32x4 v = load_chunk(A, g.lda, i0 + r, g.M, k0 + lchunk * EPC);
+            u32x4 v = load_chunk(Ap, g.lda, i0 + r, g.M, k0 + lchunk * EPC);
             if constexpr (ET == OP_F32) {
                 floatx4 f = __builtin_bit_cast(floatx4, v);
                 if (TWO_A) {
@@ -289,18 +317,18 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
                 }
                 v = __builtin_bit_cast(u32x4, f);
             }
-            ra[p] = v;
+            ra[set][p] = v;
         }
 #pragma unroll
-        for (int p = 0; p < RB; ++p) rb[p] = load_chunk(B, g.ldb, j0 + lrow + 32 * p, g.N, k0 + lchunk * EPC);
+        for (int p = 0; p < RB; ++p) rb[set][p] = load_chunk(Bp, g.ldb, j0 + lrow + 32 * p, g.N, k0 + lchunk * EPC);
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, auto set) {
         uint8_t *As = smem + buf * (BM + BN) * ROWB;
         uint8_t *Bs = As + BM * ROWB;
 #pragma unroll
-        for (int p = 0; p < RA; ++p) *(u32x4 *)&As[(lrow + 32 * p) * ROWB + lchunk * 16] = ra[p];
+        for (int p = 0; p < RA; ++p) *(u32x4 *)&As[(lrow + 32 * p) * ROWB + lchunk * 16] = ra[set][p];
 #pragma unroll
-        for (int p = 0; p < RB; ++p) *(u32x4 *)&Bs[(lrow + 32 * p) * ROWB + lchunk * 16] = rb[p];
+        for (int p = 0; p < RB; ++p) *(u32x4 *)&Bs[(lrow + 32 * p) * ROWB + lchunk * 16] = rb[set][p];
     };
 
     floatx16 acc[TM][TN];
@@ -311,14 +339,9 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-    const int nk = (g.K + BK - 1) / BK;
-    gload(0);
-    sstore(0);
-    __syncthreads();
+    const int nk = SPLIT ? 3 * (Kp / BK) : (g.K + BK - 1) / BK;
     const int frow = lane & 31, fh = lane >> 5;
-    for (int kt = 0; kt < nk; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+    auto compute = [&](int buf) {
         const uint8_t *As = smem + buf * (BM + BN) * ROWB + (wm * (BM / 2)) * ROWB + fh * 64;
         const uint8_t *Bs = smem + buf * (BM + BN) * ROWB + BM * ROWB + (wn * (BN / 2)) * ROWB + fh * 64;
 #pragma unroll
@@ -340,8 +363,33 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
                 for (int b = 0; b < TN; ++b)
                     acc[a][b] = mfma_32b<ET>(af[a][0], af[a][1], bf[b][0], bf[b][1], acc[a][b]);
         }
-        if (kt + 1 < nk) sstore(buf ^ 1);
+    };
+    gload(0, std::integral_constant<int, 0>{});
+    sstore(0, std::integral_constant<int, 0>{});
+    if constexpr (DEPTH == 2) {
+        // unrolled by two so that register sets are indexed by constants
+        if (nk > 1) gload(BK, std::integral_constant<int, 1>{});
         __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            if (kt + 2 < nk) gload((kt + 2) * BK, std::integral_constant<int, 0>{});
+            compute(0);
+            if (kt + 1 < nk) sstore(1, std::integral_constant<int, 1>{});
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            if (kt + 3 < nk) gload((kt + 3) * BK, std::integral_constant<int, 1>{});
+            compute(1);
+            if (kt + 2 < nk) sstore(0, std::integral_constant<int, 0>{});
+            __syncthreads();
+        }
+    } else {
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int buf = kt & 1;
+            if (kt + 1 < nk) gload((kt + 1) * BK, std::integral_constant<int, 0>{});
+            compute(buf);
+            if (kt + 1 < nk) sstore(buf ^ 1, std::integral_constant<int, 0>{});
+            __syncthreads();
+        }
     }
 
     // ------------------------------------------------------------ epilogue
@@ -373,7 +421,7 @@ struct TileCfg {
 };
 static const TileCfg kTiles[] = {{0, 0, ""}, {64, 4, "64"}, {128, 2, "128"}, {192, 1, "192"}, {256, 1, "256"}};
 constexpr int kNumTiles = 4;
-static const char *kTypeTag[3] = {"f32", "bf16", "fp8"};
+static const char *kTypeTag[4] = {"f32", "bf16", "fp8", "bf16x3"};
 // dense MFMA flop/s of one CU per operand type (257 = 256 CUs + 1)
 static const double kCuRate[3] = {157.3e12 / 256.0, 2516.6e12 / 256.0, 5033.2e12 / 256.0};
 
@@ -401,6 +449,10 @@ static int tile_count(int M, int N, int sym, int bm) {
 }
 
 static double model_time_us(int type, int M, int N, int K, int sym, int c) {
+    if (type == OP_BF16X3) {  // three bf16 passes
+        type = OP_BF16;
+        K *= 3;
+    }
     const double bm = kTiles[c].bm;
     const double per_cu = ceil(tile_count(M, N, sym, kTiles[c].bm) / 256.0);
     const TileModel &tm = g_model[type][sym ? 1 : 0][c];
@@ -459,6 +511,7 @@ hipError_t launch_gemm(const GemmArgs &g_in, int op_type, hipStream_t st) {
         case OP_F32: return launch_type<OP_F32>(g, st);
         case OP_BF16: return launch_type<OP_BF16>(g, st);
         case OP_FP8: return launch_type<OP_FP8>(g, st);
+        case OP_BF16X3: return launch_type<OP_BF16X3>(g, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -633,7 +686,7 @@ hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float
 // through LDS so that both the reads and the writes are row-contiguous.
 __global__ __launch_bounds__(256) void convert_tile(const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y,
                                                     int64_t ldy, int type, float scale0, int transpose,
-                                                    const Scalars *sc, int i_scale) {
+                                                    const Scalars *sc, int i_scale, int64_t plane) {
     __shared__ float tile[64][65];
     const float scale = scale0 * (sc ? scal(sc, i_scale) : 1.0f);
     const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
@@ -646,7 +699,7 @@ __global__ __launch_bounds__(256) void convert_tile(const float *X, int64_t rows
                 if (type == OP_F32)
                     ((float *)Y)[r * ldy + c] = v;
                 else
-                    store_lp(Y, type, r * ldy + c, v);
+                    store_lp(Y, type, r * ldy + c, v, plane);
             }
         } else {
             tile[k][tx] = v;
@@ -660,19 +713,19 @@ __global__ __launch_bounds__(256) void convert_tile(const float *X, int64_t rows
             if (type == OP_F32)
                 ((float *)Y)[c * ldy + r] = tile[tx][k];
             else
-                store_lp(Y, type, c * ldy + r, tile[tx][k]);
+                store_lp(Y, type, c * ldy + r, tile[tx][k], plane);
         }
     }
 }
 
 hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y, int64_t ldy, int type,
-                          float scale, int transpose, hipStream_t st, const Scalars *sc, int i_scale) {
+                          float scale, int transpose, hipStream_t st, const Scalars *sc, int i_scale, int64_t plane) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
-    if (type < 0 || type > 2) return hipErrorInvalidValue;
+    if (type < 0 || type > 3) return hipErrorInvalidValue;
     dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
     TraceScope tr(st, "convert", 0.0, (double)rows * cols * (4.0 + (type == OP_F32 ? 4 : type == OP_BF16 ? 2 : 1)));
     hipLaunchKernelGGL(convert_tile, grid, dim3(256), 0, st, X, rows, cols, ldx, Y, ldy, type, scale, transpose, sc,
-                       i_scale);
+                       i_scale, plane);
     return hipGetLastError();
 }
 

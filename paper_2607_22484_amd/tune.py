@@ -24,8 +24,10 @@ import math
 import os
 import sys
 
-CU_RATE = 157.3e12 / 256  # FP32 MFMA flop/s of one CU
+CU_RATES = {0: 157.3e12 / 256, 1: 2516.6e12 / 256, 2: 5033.2e12 / 256}  # MFMA flop/s of one CU per dtype
+CU_RATE = CU_RATES[0]
 TILES = {1: 64, 2: 128, 3: 192, 4: 256}
+DTYPES = (0, 1, 2)
 SHAPES = [  # (M, N, K, sym)
     (512, 512, 512, True), (1024, 1024, 1024, True), (2048, 2048, 2048, True), (3072, 3072, 3072, True),
     (4096, 4096, 4096, True), (4096, 4096, 8192, True), (1024, 1024, 1024, False), (2048, 2048, 2048, False),
@@ -38,19 +40,26 @@ def tile_count(M, N, bm, sym):
     return nbm * (nbm + 1) // 2 if sym else nbm * nbn
 
 
-def measure(psvt, torch, M, N, K, sym, tile, reps=5):
+def operands(psvt, torch, M, N, K, sym, dtype):
     dev = torch.device("cuda:0")
     A = torch.randn(M, K, device=dev)
     B = A if sym else torch.randn(N, K, device=dev)
-    C = torch.empty(M, N, device=dev)
+    if dtype != 0:
+        A = psvt.convert(A, dtype, scale=8.0)
+        B = A if sym else psvt.convert(B, dtype, scale=8.0)
+    return A, B, torch.empty(M, N, device=dev)
+
+
+def measure(psvt, torch, M, N, K, sym, tile, dtype=0, reps=5):
+    A, B, C = operands(psvt, torch, M, N, K, sym, dtype)
     psvt.force_tile(tile)
     try:
-        psvt.gemm_nt(A, B, sym=sym, out=C)
+        psvt.gemm_nt(A, B, sym=sym, out=C, dtype=dtype)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            psvt.gemm_nt(A, B, sym=sym, out=C)
+            psvt.gemm_nt(A, B, sym=sym, out=C, dtype=dtype)
         e1.record()
         torch.cuda.synchronize()
     finally:
@@ -59,17 +68,18 @@ def measure(psvt, torch, M, N, K, sym, tile, reps=5):
 
 
 def fit(rows):
-    """Least-squares (overhead_us, 1/eff) per (tile, sym) from measured rows."""
+    """Least-squares (overhead_us, 1/eff) per (dtype, tile, sym) from rows."""
     import numpy as np
     table = {}
-    for t, bm in TILES.items():
+    for dt in sorted(set(int(r.get("dtype", 0)) for r in rows)):
+      for t, bm in TILES.items():
         for sym in (0, 1):
             X, y = [], []
             for r in rows:
-                if int(r["sym"]) != sym:
+                if int(r["sym"]) != sym or int(r.get("dtype", 0)) != dt:
                     continue
                 per_cu = math.ceil(tile_count(r["M"], r["N"], bm, r["sym"]) / 256.0)
-                work_us = 1e6 * bm * bm * 2.0 * r["K"] / CU_RATE
+                work_us = 1e6 * bm * bm * 2.0 * r["K"] / CU_RATES[dt]
                 X.append([1.0, work_us])
                 y.append(1e6 * r["times"][t] / per_cu)
             if not X:
@@ -80,7 +90,7 @@ def fit(rows):
                 over = max(over, 0.0)
                 inv_eff = max(1.0, float(np.sum((np.array(y) - over) * np.array(X)[:, 1]) /
                                      np.sum(np.array(X)[:, 1] ** 2)))
-            table[(t, sym)] = (1.0 / inv_eff, over)
+            table[(dt, t, sym)] = (min(1.0, 1.0 / inv_eff), over)
     return table
 
 
@@ -111,19 +121,18 @@ def main():
     import paper_2607_22484_amd as psvt
     psvt.load()
     rows = []
-    effs = {t: [] for t in TILES}
-    for (M, N, K, sym) in SHAPES:
-        times = {}
-        for t, bm in TILES.items():
-            sec = measure(psvt, torch, M, N, K, sym, t)
-            per_cu = math.ceil(tile_count(M, N, bm, sym) / 256.0)
-            eff = per_cu * bm * bm * 2.0 * K / (sec * CU_RATE)
-            times[t] = sec
-            effs[t].append(eff)
-            useful = (M * (M + 1) * K if sym else 2.0 * M * N * K) / sec / 1e12
-            print("M=%d N=%d K=%d sym=%d tile=%d: %.3f ms, %.1f useful TF/s, model eff %.3f"
-                  % (M, N, K, sym, bm, sec * 1e3, useful, eff), flush=True)
-        rows.append(dict(M=M, N=N, K=K, sym=sym, times=times))
+    for dt in DTYPES:
+        for (M, N, K, sym) in SHAPES:
+            times = {}
+            for t, bm in TILES.items():
+                sec = measure(psvt, torch, M, N, K, sym, t, dt)
+                per_cu = math.ceil(tile_count(M, N, bm, sym) / 256.0)
+                eff = per_cu * bm * bm * 2.0 * K / (sec * CU_RATES[dt])
+                times[t] = sec
+                useful = (M * (M + 1) * K if sym else 2.0 * M * N * K) / sec / 1e12
+                print("dtype=%d M=%d N=%d K=%d sym=%d tile=%d: %.3f ms, %.1f useful TF/s, model eff %.3f"
+                      % (dt, M, N, K, sym, bm, sec * 1e3, useful, eff), flush=True)
+            rows.append(dict(dtype=dt, M=M, N=N, K=K, sym=sym, times=times))
     table = fit(rows)
     out = args.out or psvt.TUNE_TABLE
     write_table(out, table)
@@ -131,16 +140,16 @@ def main():
     lib.psvt_tune_load(out.encode())
     regret = []
     for r in rows:
-        pick = psvt.pick_tile(r["M"], r["N"], r["K"], r["sym"])
+        pick = psvt.pick_tile(r["M"], r["N"], r["K"], r["sym"], r["dtype"])
         best = min(r["times"], key=r["times"].get)
         regret.append(r["times"][pick] / r["times"][best])
-        print("M=%d N=%d K=%d sym=%d: model picks %d (%.3f ms), best %d (%.3f ms)"
-              % (r["M"], r["N"], r["K"], r["sym"], TILES[pick], r["times"][pick] * 1e3, TILES[best],
+        print("dtype=%d M=%d N=%d K=%d sym=%d: model picks %d (%.3f ms), best %d (%.3f ms)"
+              % (r["dtype"], r["M"], r["N"], r["K"], r["sym"], TILES[pick], r["times"][pick] * 1e3, TILES[best],
                  r["times"][best] * 1e3), flush=True)
     print("table:", table, "max regret %.3f" % max(regret), flush=True)
     if args.json:
         with open(args.json, "w") as f:
-            json.dump(dict(table={"%d_%d" % k: v for k, v in table.items()}, rows=rows), f)
+            json.dump(dict(table={"%d_%d_%d" % k: v for k, v in table.items()}, rows=rows), f)
 
 
 if __name__ == "__main__":

@@ -84,6 +84,8 @@ def test_config_validation():
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
     cfg, keep = psvt.make_config(iters=2, coeffs=[1.0, 0.0, float("nan"), 1, 0, 0])
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    cfg, _ = psvt.make_config(flags=0x4)
+    assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
 
 
 def test_empty_is_noop():
@@ -139,6 +141,7 @@ def test_tune_pick_model():
     assert lib.psvt_tune_load(psvt.TUNE_TABLE.encode()) == psvt.PSVT_OK
     assert psvt.pick_tile(4096, 4096, 4096, True) == psvt.TILE_IDS[192]
     assert psvt.pick_tile(4096, 4096, 4096, False) == psvt.TILE_IDS[256]
+    assert psvt.pick_tile(4096, 4096, 4096, True, dtype=psvt.DTYPE_BF16) == psvt.TILE_IDS[192]
     assert psvt.pick_tile(512, 512, 512, True) == psvt.TILE_IDS[64]
     assert lib.psvt_tune_pick(0, 0, 5, 5, 0) == psvt.PSVT_EINVAL
     assert lib.psvt_tune_pick(7, 5, 5, 5, 0) == psvt.PSVT_EINVAL
