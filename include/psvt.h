@@ -123,6 +123,77 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
 int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy, void *ws,
                 size_t ws_bytes, const psvt_config *cfg, void *stream);
 
+/* Batched form: many svt (or rank_r) problems of uneven shapes.
+ *
+ * psvt_batch_create plans the batch on the host: every item runs the same
+ * stage list, and stage k of all items becomes grouped launches (products
+ * grouped by the tile configuration the autotuned cost model picks for each
+ * item's size, largest first, blocks mapped to (item, tile) through a prefix
+ * sum).  It copies the descriptor tables to a device buffer it allocates, and
+ * captures one run into a HIP graph; it synchronises and allocates, so call
+ * it outside graph capture.  Items are read through their pointers at run
+ * time, so their contents may change between runs.
+ * psvt_batch_run enqueues the grouped launches on `stream`;
+ * psvt_batch_run_graph replays the captured graph on `stream` (one graph
+ * launch).  Neither allocates or synchronises.  Runs of one batch must not
+ * overlap (they share `ws`).
+ * `ws`: caller-owned device memory of psvt_batch_workspace_bytes(), 256-byte
+ * aligned, that must outlive the batch.  op: PSVT_OP_SVT or PSVT_OP_RANK_R. */
+typedef struct psvt_batch_item {
+    const float *A; /* m x n input, row-major, device */
+    float *Y;       /* m x n output, row-major, device */
+    int64_t m, n, lda, ldy;
+    double tau;
+} psvt_batch_item;
+typedef struct psvt_batch psvt_batch;
+int psvt_batch_workspace_bytes(int op, const psvt_batch_item *items, int32_t count, const psvt_config *cfg,
+                               size_t *bytes);
+int psvt_batch_create(int op, const psvt_batch_item *items, int32_t count, void *ws, size_t ws_bytes,
+                      const psvt_config *cfg, psvt_batch **out);
+int psvt_batch_run(psvt_batch *batch, void *stream);
+int psvt_batch_run_graph(psvt_batch *batch, void *stream);
+/* number of grouped launches per run and useful flops per run */
+int psvt_batch_stats(const psvt_batch *batch, int32_t *launches, double *flops);
+int psvt_batch_destroy(psvt_batch *batch);
+
+/* Serving: a request loop for svt / rank_r calls of mixed sizes.
+ *
+ * A server owns a device memory pool of `budget_bytes` (the HBM budget) and
+ * a worker thread.  Requests are admitted in arrival order while fewer than
+ * `max_slots` are active and the pool has room for the request's workspace
+ * (a request never overtakes an earlier one).  An admitted request's
+ * iterates stay in its workspace on the device until it completes.  The
+ * worker runs ticks: every active request advances by up to 3 stages of its
+ * stage list; a round's stages are grouped by kind (products also by operand
+ * type and tile configuration) into grouped launches, so requests at
+ * different points of their iteration share launches and newcomers join at
+ * the next tick (iteration-level continuous batching).  Tiles are computed
+ * exactly as in single calls, so a result is the same alone and in the mix.
+ * All requests use the server's psvt_config (its coeffs are copied).
+ *   create:  allocates the pool and its stream; PSVT_SERVER_FAKE runs the
+ *            scheduler without a device (stages complete at once; for tests).
+ *   submit:  non-blocking; A is read and Y written by the device at some
+ *            later time, so both must stay valid until the request is done.
+ *            PSVT_EWORKSPACE if the request could never fit the budget.
+ *   poll / wait:  state 0 queued, 1 running, 2 done, -1 failed.
+ *   drain:   waits until nothing is queued or active.
+ *   stats:   latency = completion observed by the worker - submit time. */
+#define PSVT_SERVER_FAKE 0x1u
+typedef struct psvt_server psvt_server;
+typedef struct psvt_server_counters {
+    int64_t submitted, completed, failed, queued, active, ticks, launches;
+    double p50_ms, p99_ms, max_ms, queue_p99_ms, matrices_per_s;
+    size_t budget_bytes, peak_bytes;
+} psvt_server_counters;
+int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config *cfg, uint32_t flags,
+                       psvt_server **out);
+int psvt_server_submit(psvt_server *server, int op, const psvt_batch_item *item, uint64_t *ticket);
+int psvt_server_poll(psvt_server *server, uint64_t ticket, int32_t *state);
+int psvt_server_wait(psvt_server *server, uint64_t ticket, double timeout_s, int32_t *state);
+int psvt_server_drain(psvt_server *server, double timeout_s);
+int psvt_server_stats(psvt_server *server, psvt_server_counters *stats);
+int psvt_server_destroy(psvt_server *server);
+
 /* Building blocks exposed for kernel-level tests and tuning.
  *
  * psvt_gemm_nt: the MFMA product used by every step of the method,

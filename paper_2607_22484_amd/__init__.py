@@ -32,7 +32,12 @@ EXPORTED = [
     "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
     "psvt_strerror", "psvt_last_error", "psvt_version", "psvt_trace_begin", "psvt_trace_end",
     "psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick",
+    "psvt_batch_workspace_bytes", "psvt_batch_create", "psvt_batch_run", "psvt_batch_run_graph", "psvt_batch_stats",
+    "psvt_batch_destroy", "psvt_server_create", "psvt_server_submit", "psvt_server_poll", "psvt_server_wait",
+    "psvt_server_drain", "psvt_server_stats", "psvt_server_destroy",
 ]
+SERVER_FAKE = 0x1
+RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_FAILED = 0, 1, 2, -1
 TILE_IDS = {64: 1, 128: 2, 192: 3, 256: 4}
 TUNE_TABLE = os.path.join(_HERE, "tune_table.txt")
 
@@ -54,6 +59,20 @@ class Config(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("reserved", ctypes.c_int32 * 3),
     ]
+
+
+class BatchItem(ctypes.Structure):
+    """Mirror of ``psvt_batch_item``."""
+    _fields_ = [("A", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("ldy", ctypes.c_int64), ("tau", ctypes.c_double)]
+
+
+class ServerCounters(ctypes.Structure):
+    """Mirror of ``psvt_server_counters``."""
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "queued", "active", "ticks",
+                                              "launches")] + \
+               [(k, ctypes.c_double) for k in ("p50_ms", "p99_ms", "max_ms", "queue_p99_ms", "matrices_per_s")] + \
+               [("budget_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
 
 
 class TraceStat(ctypes.Structure):
@@ -96,6 +115,30 @@ def load(path: Optional[str] = None):
     lib.psvt_tune_load.argtypes = [ctypes.c_char_p]
     lib.psvt_tune_pick.argtypes = [ctypes.c_int, i64, i64, i64, ctypes.c_int]
     for f in ("psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick"):
+        getattr(lib, f).restype = ctypes.c_int
+    items_p = ctypes.POINTER(BatchItem)
+    lib.psvt_batch_workspace_bytes.argtypes = [ctypes.c_int, items_p, ctypes.c_int32, cfgp,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+    lib.psvt_batch_create.argtypes = [ctypes.c_int, items_p, ctypes.c_int32, vp, ctypes.c_size_t, cfgp,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+    lib.psvt_batch_run.argtypes = [vp, vp]
+    lib.psvt_batch_run_graph.argtypes = [vp, vp]
+    lib.psvt_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.psvt_batch_destroy.argtypes = [vp]
+    for f in ("psvt_batch_workspace_bytes", "psvt_batch_create", "psvt_batch_run", "psvt_batch_run_graph",
+              "psvt_batch_stats", "psvt_batch_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
+    srv = ctypes.c_void_p
+    lib.psvt_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, cfgp, ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.c_void_p)]
+    lib.psvt_server_submit.argtypes = [srv, ctypes.c_int, items_p, ctypes.POINTER(ctypes.c_uint64)]
+    lib.psvt_server_poll.argtypes = [srv, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
+    lib.psvt_server_wait.argtypes = [srv, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
+    lib.psvt_server_drain.argtypes = [srv, ctypes.c_double]
+    lib.psvt_server_stats.argtypes = [srv, ctypes.POINTER(ServerCounters)]
+    lib.psvt_server_destroy.argtypes = [srv]
+    for f in ("psvt_server_create", "psvt_server_submit", "psvt_server_poll", "psvt_server_wait",
+              "psvt_server_drain", "psvt_server_stats", "psvt_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     lib.psvt_trace_begin.restype = ctypes.c_int
     lib.psvt_trace_end.restype = ctypes.c_int
@@ -305,6 +348,136 @@ def convert(X, dtype: int, scale: float = 1.0, transpose: bool = False, out=None
         _check(load().psvt_convert(int(dtype), X.data_ptr(), rows, cols, _ld(X), Y.data_ptr(), _ld_any(Y),
                                    float(scale), 1 if transpose else 0, _stream_ptr(X)), "psvt_convert")
     return Y
+
+
+class Batch:
+    """Batched soft-thresholding of many uneven matrices (C ABI psvt_batch_*).
+
+    ``As``: list of 2-D float32 GPU tensors; ``taus``: thresholds.  Outputs
+    are allocated here (``Ys``).  ``run()`` enqueues the grouped launches,
+    ``run_graph()`` replays the captured graph; both on the current stream."""
+
+    def __init__(self, As, taus, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, op: int = OP_SVT,
+                 flags: int = 0, side: int = SIDE_AUTO):
+        torch = _torch()
+        if len(As) != len(taus) or not As:
+            raise ValueError("need one tau per matrix")
+        for A in As:
+            _check_input(A)
+        self.As = list(As)
+        self.Ys = [torch.empty_like(A) for A in As]
+        items = (BatchItem * len(As))()
+        for i, (A, Y, tau) in enumerate(zip(self.As, self.Ys, taus)):
+            items[i] = BatchItem(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), float(tau))
+        self._items = items
+        self.cfg, self._keep = make_config(iters, n_fp8, n_bf16, side, None, flags)
+        lib = load()
+        need = ctypes.c_size_t(0)
+        _check(lib.psvt_batch_workspace_bytes(op, items, len(As), ctypes.byref(self.cfg), ctypes.byref(need)),
+               "psvt_batch_workspace_bytes")
+        dev = As[0].device
+        self.ws = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=dev)
+        self.device = dev
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            _check(lib.psvt_batch_create(op, items, len(As), self.ws.data_ptr(), int(need.value),
+                                         ctypes.byref(self.cfg), ctypes.byref(h)), "psvt_batch_create")
+        self._h = h
+
+    def run(self):
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            _check(load().psvt_batch_run(self._h, _stream_ptr(self.As[0])), "psvt_batch_run")
+        return self.Ys
+
+    def run_graph(self):
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            _check(load().psvt_batch_run_graph(self._h, _stream_ptr(self.As[0])), "psvt_batch_run_graph")
+        return self.Ys
+
+    def stats(self):
+        n = ctypes.c_int32(0)
+        f = ctypes.c_double(0.0)
+        _check(load().psvt_batch_stats(self._h, ctypes.byref(n), ctypes.byref(f)), "psvt_batch_stats")
+        return int(n.value), float(f.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().psvt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (C ABI psvt_server_*): admission by an HBM budget,
+    iteration-level continuous batching, latency statistics."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 64, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0,
+                 flags: int = 0, fake: bool = False, side: int = SIDE_AUTO):
+        self.cfg, self._keep = make_config(iters, n_fp8, n_bf16, side, None, flags)
+        h = ctypes.c_void_p()
+        _check(load().psvt_server_create(int(budget_bytes), int(max_slots), ctypes.byref(self.cfg),
+                                         SERVER_FAKE if fake else 0, ctypes.byref(h)), "psvt_server_create")
+        self._h = h
+        self._pinned = {}
+
+    def submit_ptr(self, A_ptr: int, Y_ptr: int, m: int, n: int, lda: int, ldy: int, tau: float,
+                   op: int = OP_SVT) -> int:
+        item = BatchItem(A_ptr, Y_ptr, m, n, lda, ldy, float(tau))
+        t = ctypes.c_uint64(0)
+        _check(load().psvt_server_submit(self._h, op, ctypes.byref(item), ctypes.byref(t)), "psvt_server_submit")
+        return int(t.value)
+
+    def submit(self, A, tau: float, out=None, op: int = OP_SVT):
+        """Submit A (float32 GPU tensor); returns (ticket, Y).  Keep A and Y
+        alive until the ticket is done."""
+        torch = _torch()
+        _check_input(A)
+        Y = out if out is not None else torch.empty_like(A)
+        t = self.submit_ptr(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), tau, op)
+        self._pinned[t] = (A, Y)
+        return t, Y
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int32(0)
+        _check(load().psvt_server_poll(self._h, ticket, ctypes.byref(st)), "psvt_server_poll")
+        if st.value in (RQ_DONE, RQ_FAILED):
+            self._pinned.pop(ticket, None)
+        return int(st.value)
+
+    def wait(self, ticket: int, timeout: float = 60.0) -> int:
+        st = ctypes.c_int32(0)
+        _check(load().psvt_server_wait(self._h, ticket, float(timeout), ctypes.byref(st)), "psvt_server_wait")
+        if st.value in (RQ_DONE, RQ_FAILED):
+            self._pinned.pop(ticket, None)
+        return int(st.value)
+
+    def drain(self, timeout: float = 600.0):
+        _check(load().psvt_server_drain(self._h, float(timeout)), "psvt_server_drain")
+        self._pinned.clear()
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(load().psvt_server_stats(self._h, ctypes.byref(c)), "psvt_server_stats")
+        return {k: getattr(c, k) for k, _ in ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().psvt_server_destroy(self._h)
+            self._h = None
+            self._pinned.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def trace_begin():

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpsvt.so")
-SOURCES = ["api.hip", "kernels.hip", "trace.hip"]
+SOURCES = ["api.hip", "kernels.hip", "trace.hip", "batch.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled: the compiler must not form

@@ -33,6 +33,7 @@
 #include "../../include/psvt.h"
 #include "coeffs.h"
 #include "kernels.h"
+#include "plan.h"
 
 using namespace psvt;
 
@@ -321,7 +322,7 @@ float *F(void *ws, size_t off) { return (float *)at(ws, off); }
 
 // symmetric product C = alpha A B^T + beta D (+ diag I), A, B, C, D s x s
 hipError_t syrk(const float *A, const float *B, int64_t ld, const float *D, float *C, int64_t ldc, int64_t s,
-                float alpha, int i_alpha, float beta, int i_beta, float diag, const Scalars *sc, hipStream_t st) {
+                float alpha, int i_alpha, float beta, int i_beta, float diag, const Scalars *sc, Exec &ex) {
     GemmArgs g = gemm_defaults();
     g.A = A;
     g.B = B;
@@ -339,21 +340,21 @@ hipError_t syrk(const float *A, const float *B, int64_t ld, const float *D, floa
     g.diag = diag;
     g.sc = sc;
     g.sym = 1;
-    return launch_gemm(g, OP_F32, st);
+    return ex.gemm(g, OP_F32, "syrk");
 }
 
 // Gram prelude shared by svt / polar / rank_r: nu, X0, X0^T, T, theta_P.
 int prelude(const float *A, int64_t m, int64_t n, int64_t lda, double tau, const Layout &L, void *ws,
-            hipStream_t st, bool want_theta_p) {
+            Exec &ex, bool want_theta_p) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     double *part = (double *)at(ws, L.part);
-    HIP_TRY(launch_fro_norm(A, m, n, lda, part, sc, NORM_INPUT, tau, st), "norm of A");
+    HIP_TRY(ex.norm(make_norm_op(A, m, n, lda, part, sc, NORM_INPUT, tau), "norm of A"), "norm of A");
     float *X0 = F(ws, L.X0), *X0T = F(ws, L.X0T);
     // right: X = A -> X0 = A/nu (copy), X0T = A^T/nu; left: X = A^T -> swapped
     if (L.right)
-        HIP_TRY(launch_scale_transpose(A, m, n, lda, X0, L.ldS, X0T, L.ldL, sc, F_INV_NU, st), "scale A");
+        HIP_TRY(ex.tile(make_scale_transpose(A, m, n, lda, X0, L.ldS, X0T, L.ldL, sc, F_INV_NU), "scale A"), "scale A");
     else
-        HIP_TRY(launch_scale_transpose(A, m, n, lda, X0T, L.ldL, X0, L.ldS, sc, F_INV_NU, st), "scale A");
+        HIP_TRY(ex.tile(make_scale_transpose(A, m, n, lda, X0T, L.ldL, X0, L.ldS, sc, F_INV_NU), "scale A"), "scale A");
     // T = X0^T X0 = (X0^T)(X0^T)^T : NT product of the s x l transposed copy
     GemmArgs g = gemm_defaults();
     g.A = X0T;
@@ -365,9 +366,9 @@ int prelude(const float *A, int64_t m, int64_t n, int64_t lda, double tau, const
     g.K = (int)L.l;
     g.sc = sc;
     g.sym = 1;
-    HIP_TRY(launch_gemm(g, OP_F32, st), "Gram");
+    HIP_TRY(ex.gemm(g, OP_F32, "Gram"), "Gram");
     if (want_theta_p)
-        HIP_TRY(launch_fro_norm(F(ws, L.T), L.s, L.s, L.ldS, part, sc, NORM_THETA_P, 0.0, st), "theta_P");
+        HIP_TRY(ex.norm(make_norm_op(F(ws, L.T), L.s, L.s, L.ldS, part, sc, NORM_THETA_P, 0.0), "theta_P"), "theta_P");
     return PSVT_OK;
 }
 
@@ -399,7 +400,7 @@ void set_lp_out(GemmArgs &g, int type, void *row, int64_t ldrow, void *trans, in
 // (from the copy of T, with the FP32 T as the b-term), X' = a X + X B (from
 // the copies of X and B, with the FP32 X as the a-term).  Each product writes
 // the copies its consumer needs, in the consumer's type.
-int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, float *user_out, int64_t ld_out,
+int polar_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, float *user_out, int64_t ld_out,
                      const float **out_P) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     IterScale scl[257];
@@ -422,8 +423,8 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
                     sB = dt == OP_FP8 ? scl[t].sB : 1.0f, sXn = nd == OP_FP8 ? scl[t + 1].sX : 1.0f;
         if (first && lp) {
             // theta is folded into the first copies: X0 / theta and T / theta^2
-            HIP_TRY(launch_convert(curX, L.l, L.s, L.ldS, bufXlp[1], L.ldS, dt, sX, 0, st, sc, F_P1, L.planeX), "P: X0 copy");
-            HIP_TRY(launch_convert(T, L.s, L.s, L.ldS, Tlp, L.ldS, dt, sT, 0, st, sc, F_P2, L.planeS), "P: T copy");
+            HIP_TRY(ex.tile(make_convert(curX, L.l, L.s, L.ldS, bufXlp[1], L.ldS, dt, sX, 0, sc, F_P1, L.planeX), "P: X0 copy"), "P: X0 copy");
+            HIP_TRY(ex.tile(make_convert(T, L.s, L.s, L.ldS, Tlp, L.ldS, dt, sT, 0, sc, F_P2, L.planeS), "P: T copy"), "P: T copy");
             curXlp = bufXlp[1];
         }
         if (!first) {  // T = X^T X
@@ -439,7 +440,7 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
             g.sym = 1;
             set_operand_scales(g, dt, sX, sX);
             if (lp) set_lp_out(g, dt, Tlp, L.ldS, nullptr, 0, sT, L.planeS);
-            HIP_TRY(launch_gemm(g, dt, st), "P: X^T X");
+            HIP_TRY(ex.gemm(g, dt, "P: X^T X"), "P: X^T X");
         }
         {  // B = c T^2 + b T   (first iteration: theta scaling through device scalars)
             GemmArgs g = gemm_defaults();
@@ -462,7 +463,7 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
                 g.C = Bm;
                 g.ldc = L.ldS;
             }
-            HIP_TRY(launch_gemm(g, dt, st), "P: b T + c T^2");
+            HIP_TRY(ex.gemm(g, dt, "P: b T + c T^2"), "P: b T + c T^2");
         }
         {  // X' = a X + X B   (first iteration: times 1/theta)
             GemmArgs g = gemm_defaults();
@@ -504,7 +505,7 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
                     }
                 }
             }
-            HIP_TRY(launch_gemm(g, dt, st), "P: a X + X B");
+            HIP_TRY(ex.gemm(g, dt, "P: a X + X B"), "P: a X + X B");
             curX = bufX[k];
             curXT = bufXT[k];
             curXlp = bufXlp[k];
@@ -518,7 +519,7 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, fl
 // S iterations from H (s x s, ld = ldS) with R = H^2 and theta_S already in
 // the scalar block.  want_pi: the last iteration writes (I + S)/2.  Same
 // precision scheme as the P iterations, with X^2 in place of X^T X.
-int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, bool want_pi, float *user_out,
+int sign_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, bool want_pi, float *user_out,
                     int64_t ld_out, const float **out_S) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     IterScale scl[257];
@@ -539,8 +540,8 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
         const float sX = dt == OP_FP8 ? scl[t].sX : 1.0f, sT = dt == OP_FP8 ? scl[t].sT : 1.0f,
                     sB = dt == OP_FP8 ? scl[t].sB : 1.0f, sXn = nd == OP_FP8 ? scl[t + 1].sX : 1.0f;
         if (first && lp) {
-            HIP_TRY(launch_convert(cur, s, s, ld, buflp[1], ld, dt, sX, 0, st, sc, F_S1, L.planeS), "S: H copy");
-            HIP_TRY(launch_convert(R, s, s, ld, X2lp, ld, dt, sT, 0, st, sc, F_S2, L.planeS), "S: H^2 copy");
+            HIP_TRY(ex.tile(make_convert(cur, s, s, ld, buflp[1], ld, dt, sX, 0, sc, F_S1, L.planeS), "S: H copy"), "S: H copy");
+            HIP_TRY(ex.tile(make_convert(R, s, s, ld, X2lp, ld, dt, sT, 0, sc, F_S2, L.planeS), "S: H^2 copy"), "S: H^2 copy");
             curlp = buflp[1];
         }
         const float *sq = R;
@@ -556,7 +557,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
             g.sym = 1;
             set_operand_scales(g, dt, sX, sX);
             if (lp) set_lp_out(g, dt, X2lp, ld, nullptr, 0, sT, L.planeS);
-            HIP_TRY(launch_gemm(g, dt, st), "S: X^2");
+            HIP_TRY(ex.gemm(g, dt, "S: X^2"), "S: X^2");
             sq = X2;
         }
         {  // B = c X^4 + b X^2
@@ -580,7 +581,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
                 g.C = BS;
                 g.ldc = ld;
             }
-            HIP_TRY(launch_gemm(g, dt, st), "S: b X^2 + c X^4");
+            HIP_TRY(ex.gemm(g, dt, "S: b X^2 + c X^4"), "S: b X^2 + c X^4");
         }
         {  // X' = a X + B X  (symmetric: B and X commute)
             float alpha = 1.0f, beta = a, diag = 0.0f;
@@ -610,7 +611,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
             g.C = dst;
             g.ldc = (last && user_out) ? ld_out : ld;
             if (!last && nd != OP_F32) set_lp_out(g, nd, buflp[k], ld, nullptr, 0, sXn, L.planeS);
-            HIP_TRY(launch_gemm(g, dt, st), "S: a X + B X");
+            HIP_TRY(ex.gemm(g, dt, "S: a X + B X"), "S: a X + B X");
             cur = dst;
             curlp = buflp[k];
         }
@@ -620,19 +621,19 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, hipStream_t st, boo
 }
 
 // H = T - (tau/nu)^2 I, R = H^2, theta_S
-int shifted_gram(const Layout &L, void *ws, hipStream_t st) {
+int shifted_gram(const Layout &L, void *ws, Exec &ex) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     double *part = (double *)at(ws, L.part);
-    HIP_TRY(launch_shift_copy(F(ws, L.T), L.s, L.ldS, F(ws, L.H), L.ldS, sc, st), "shift");
-    HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, L.s, 1.0f, -1, 0.0f, -1, 0.0f, sc, st),
+    HIP_TRY(ex.tile(make_shift_copy(F(ws, L.T), L.s, L.ldS, F(ws, L.H), L.ldS, sc), "shift"), "shift");
+    HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, L.s, 1.0f, -1, 0.0f, -1, 0.0f, sc, ex),
             "H^2");
-    HIP_TRY(launch_fro_norm(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_THETA_S, 0.0, st), "theta_S");
+    HIP_TRY(ex.norm(make_norm_op(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_THETA_S, 0.0), "theta_S"), "theta_S");
     return PSVT_OK;
 }
 
 // Y = (nu X0 [- tau P]) Pi, written transposed for the left-sided case.
 int final_product(const Layout &L, void *ws, const float *P, double tau, const float *Pi, float *Y, int64_t ldy,
-                  hipStream_t st) {
+                  Exec &ex) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     GemmArgs g = gemm_defaults();
     g.A = F(ws, L.X0);
@@ -657,7 +658,7 @@ int final_product(const Layout &L, void *ws, const float *P, double tau, const f
         g.CT = Y;
         g.ldct = ldy;
     }
-    HIP_TRY(launch_gemm(g, OP_F32, st), "final product");
+    HIP_TRY(ex.gemm(g, OP_F32, "final product"), "final product");
     return PSVT_OK;
 }
 
@@ -667,6 +668,19 @@ int check_ws(void *ws, size_t ws_bytes, const Layout &L) {
         return fail(PSVT_EWORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
     if (((uintptr_t)ws & 255) != 0) return fail(PSVT_EINVAL, "workspace is not 256-byte aligned");
     return PSVT_OK;
+}
+
+// The stage list of svt / rank_r (Proposition 1 / Corollary 1).
+int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
+                  void *ws, const Layout &L, const Cfg &c, Exec &ex) {
+    int rc;
+    if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, op == PSVT_OP_SVT))) return rc;
+    if ((rc = shifted_gram(L, ws, ex))) return rc;
+    const float *P = nullptr, *Pi = nullptr;
+    if (op == PSVT_OP_SVT)
+        if ((rc = polar_iterations(c, L, ws, ex, nullptr, 0, &P))) return rc;
+    if ((rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi))) return rc;
+    return final_product(L, ws, P, tau, Pi, Y, ldy, ex);
 }
 
 int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
@@ -685,17 +699,39 @@ int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double t
         overlaps(Y, span_bytes(m, n, ldy), ws, L.total) || overlaps(A, span_bytes(m, n, lda), ws, L.total))
         return fail(PSVT_EINVAL, "Y, A and ws must not overlap");
     if ((rc = check_device())) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    if ((rc = prelude(A, m, n, lda, tau, L, ws, st, op == PSVT_OP_SVT))) return rc;
-    if ((rc = shifted_gram(L, ws, st))) return rc;
-    const float *P = nullptr, *Pi = nullptr;
-    if (op == PSVT_OP_SVT)
-        if ((rc = polar_iterations(c, L, ws, st, nullptr, 0, &P))) return rc;
-    if ((rc = sign_iterations(c, L, ws, st, true, nullptr, 0, &Pi))) return rc;
-    return final_product(L, ws, P, tau, Pi, Y, ldy, st);
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    return plan_svt_like(op, A, m, n, lda, tau, Y, ldy, ws, L, c, ex);
 }
 
 }  // namespace
+
+namespace psvt {
+
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+// Stage list of one batch item (records, launches nothing).  ws == NULL:
+// only report the workspace size.
+int plan_request(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, std::vector<Stage> &out,
+                 size_t *ws_bytes, bool check_dev) {
+    Cfg c;
+    int rc = read_cfg(cfg, c);
+    if (rc) return rc;
+    Layout L = make_layout(op, it.m, it.n, c);
+    *ws_bytes = L.total;
+    if (!ws) return PSVT_OK;
+    if (check_dev && (rc = check_device())) return rc;
+    Exec ex;
+    ex.rec = &out;
+    return plan_svt_like(op, it.A, it.m, it.n, it.lda, it.tau, it.Y, it.ldy, ws, L, c, ex);
+}
+
+int batch_plan_one(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, std::vector<Stage> &out,
+                   size_t *ws_bytes) {
+    return plan_request(op, it, ws, cfg, out, ws_bytes, true);
+}
+
+}  // namespace psvt
 
 extern "C" {
 
@@ -741,9 +777,10 @@ int psvt_polar(const float *A, int64_t m, int64_t n, int64_t lda, float *P, int6
         overlaps(P, span_bytes(m, n, ldp), ws, L.total) || overlaps(A, span_bytes(m, n, lda), ws, L.total))
         return fail(PSVT_EINVAL, "P, A and ws must not overlap");
     if ((rc = check_device())) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    if ((rc = prelude(A, m, n, lda, 0.0, L, ws, st, true))) return rc;
-    return polar_iterations(c, L, ws, st, P, ldp, nullptr);
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    if ((rc = prelude(A, m, n, lda, 0.0, L, ws, ex, true))) return rc;
+    return polar_iterations(c, L, ws, ex, P, ldp, nullptr);
 }
 
 int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds, void *ws, size_t ws_bytes,
@@ -761,15 +798,16 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
         overlaps(S, span_bytes(n, n, lds), ws, L.total) || overlaps(G, span_bytes(n, n, ldg), ws, L.total))
         return fail(PSVT_EINVAL, "S, G and ws must not overlap");
     if ((rc = check_device())) return rc;
-    hipStream_t st = (hipStream_t)stream;
+    Exec ex;
+    ex.st = (hipStream_t)stream;
     Scalars *sc = (Scalars *)at(ws, L.scal);
     double *part = (double *)at(ws, L.part);
-    HIP_TRY(launch_fro_norm(G, n, n, ldg, part, sc, NORM_INPUT, 0.0, st), "norm of G");
-    HIP_TRY(launch_symmetrize_scale(G, n, ldg, F(ws, L.H), L.ldS, sc, st), "symmetrize");
-    HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, n, 1.0f, -1, 0.0f, -1, 0.0f, sc, st),
+    HIP_TRY(ex.norm(make_norm_op(G, n, n, ldg, part, sc, NORM_INPUT, 0.0), "norm of G"), "norm of G");
+    HIP_TRY(ex.tile(make_symmetrize_scale(G, n, ldg, F(ws, L.H), L.ldS, sc), "symmetrize"), "symmetrize");
+    HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, n, 1.0f, -1, 0.0f, -1, 0.0f, sc, ex),
             "G^2");
-    HIP_TRY(launch_fro_norm(F(ws, L.R), n, n, L.ldS, part, sc, NORM_THETA_S, 0.0, st), "theta_S");
-    return sign_iterations(c, L, ws, st, false, S, lds, nullptr);
+    HIP_TRY(ex.norm(make_norm_op(F(ws, L.R), n, n, L.ldS, part, sc, NORM_THETA_S, 0.0), "theta_S"), "theta_S");
+    return sign_iterations(c, L, ws, ex, false, S, lds, nullptr);
 }
 
 int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb, const float *D, int64_t ldd,

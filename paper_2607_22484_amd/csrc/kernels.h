@@ -68,6 +68,36 @@ struct GemmArgs {
     int64_t lp_plane, lp_plane_t;  // OP_BF16X3 copies Clp / CTlp: elements from the hi to the lo plane
 };
 
+// One Frobenius-norm reduction (FP64) and the scalars derived from it.
+struct NormOp {
+    const float *X;
+    int64_t rows, cols, ld;
+    double *part;  // nparts partial sums
+    int nparts;
+    Scalars *sc;
+    int mode;
+    double tau;
+};
+
+// One 64x64-tiled elementwise pass (see kernels.hip, tile ops).
+enum TileOpKind { TOP_SCALE_T = 0, TOP_SHIFT = 1, TOP_SYMM = 2, TOP_CONVERT = 3 };
+struct TileOp {
+    int kind;
+    const float *X;
+    int64_t rows, cols, ldx;
+    float *Y;
+    int64_t ldy;
+    float *YT;
+    int64_t ldyt;
+    void *L;
+    int64_t ldl;
+    int ltype, ltrans;
+    int64_t lplane;
+    float scale;
+    const Scalars *sc;
+    int i_scale;
+};
+
 // Launchers (enqueue only).  Return a hipError_t.
 hipError_t launch_gemm(const GemmArgs &g, int op_type, hipStream_t st);
 hipError_t launch_fro_norm(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials,
@@ -82,6 +112,29 @@ hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float
 hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy,
                           int op_type, float scale, int transpose, hipStream_t st, const Scalars *sc = nullptr,
                           int i_scale = -1, int64_t plane = 0);
+
+NormOp make_norm_op(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials, Scalars *sc, int mode,
+                    double tau);
+hipError_t launch_norm_op(const NormOp &op, hipStream_t st);
+hipError_t launch_norm_grouped(const NormOp *ops, const int *prefix, int n, int total_blocks, double bytes,
+                               hipStream_t st);
+TileOp make_scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda, float *Y, int64_t ldy, float *YT,
+                            int64_t ldyt, const Scalars *sc, int i_scale);
+TileOp make_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc);
+TileOp make_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, int64_t ldh, const Scalars *sc);
+TileOp make_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy, int type,
+                    float scale, int transpose, const Scalars *sc, int i_scale, int64_t plane);
+hipError_t launch_tile_op(const TileOp &op, hipStream_t st);
+hipError_t launch_tile_op_grouped(const TileOp *ops, const int *prefix, int n, int total, int kind, double bytes,
+                                  hipStream_t st);
+int tile_op_tiles(const TileOp &op);
+double tile_op_bytes(const TileOp &op);
+hipError_t launch_gemm_grouped(const GemmArgs *args, const int *prefix, int n, int total, int op_type, int tile,
+                               int sym, int two_a, double flops, hipStream_t st);
+int gemm_pick_tile(const GemmArgs &g, int op_type);
+int gemm_tile_count(const GemmArgs &g, int tile);
+double gemm_model_us(const GemmArgs &g, int op_type, int tile);
+void gemm_prepare(GemmArgs &g);
 
 // modes for launch_fro_norm
 enum NormMode {

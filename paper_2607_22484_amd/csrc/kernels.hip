@@ -227,25 +227,31 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j,
 // is order-free, so lane half h takes bytes [64h, 64h + 64) of its rows in
 // every k-tile: four 16-byte LDS reads per row.  f32 feeds 1 element per
 // MFMA (16 MFMAs per k-tile), bf16 8 (4 MFMAs), fp8 32 (2 MFMAs).
-template <int ET, int BM, int BN, int OCC, bool TWO_A, bool SYM>
-__global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
+template <int ET, int BM, int BN>
+struct TileShape {
+    static constexpr int ROWB = 144;  // LDS row stride in bytes
+    static constexpr int SMEM = 2 * (BM + BN) * ROWB;
+};
+
+// Local tile t of a product -> block tile (bi, bj): lower block triangle for
+// SYM, grouped row-major order otherwise.
+template <bool SYM>
+__device__ __forceinline__ void tile_coords(int t, int M, int N, int BM, int BN, int &bi, int &bj) {
+    if (SYM)
+        tri_index(t, bi, bj);
+    else
+        grouped_index<8>(t, (M + BM - 1) / BM, (N + BN - 1) / BN, bi, bj);
+}
+
+// One BM x BN output tile of the product described by g.
+template <int ET, int BM, int BN, bool TWO_A, bool SYM>
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uint8_t *smem) {
     typedef typename Op<ET>::T T;
     constexpr int EPC = Op<ET>::EPC;
     constexpr int BK = 8 * EPC;        // elements per k-tile
-    constexpr int ROWB = 144;          // LDS row stride in bytes
+    constexpr int ROWB = TileShape<ET, BM, BN>::ROWB;
     constexpr int TM = BM / 64, TN = BN / 64;
     constexpr int RA = BM / 32, RB = BN / 32;  // 16-byte loads per thread
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * (BM + BN) * ROWB];
-
-    const int nbm = (g.M + BM - 1) / BM, nbn = (g.N + BN - 1) / BN;
-    int bi, bj;
-    {
-        const int t = xcd_remap(blockIdx.x, gridDim.x);
-        if (SYM)
-            tri_index(t, bi, bj);
-        else
-            grouped_index<8>(t, nbm, nbn, bi, bj);
-    }
     const int i0 = bi * BM, j0 = bj * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -412,6 +418,38 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
     });
 }
 
+// One product: block b computes local tile xcd_remap(b) (each XCD gets a
+// contiguous range of tiles, so tiles sharing panels share an L2).
+template <int ET, int BM, int BN, int OCC, bool TWO_A, bool SYM>
+__global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint8_t smem[TileShape<ET, BM, BN>::SMEM];
+    int bi, bj;
+    tile_coords<SYM>(xcd_remap(blockIdx.x, gridDim.x), g.M, g.N, BM, BN, bi, bj);
+    gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
+}
+
+// Many products of one kind in one launch (batched and serving forms):
+// prefix[p] = tiles of products 0..p-1; block b finds its product by binary
+// search, so the hardware dispatcher balances uneven products (they are
+// ordered largest first).
+template <int ET, int BM, int BN, int OCC, bool TWO_A, bool SYM>
+__global__ __launch_bounds__(256, OCC) void gemm_grouped(const GemmArgs *args, const int *prefix, int nprob) {
+    __shared__ __attribute__((aligned(16))) uint8_t smem[TileShape<ET, BM, BN>::SMEM];
+    const int b = blockIdx.x;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {  // last p with prefix[p] <= b
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const GemmArgs &g = args[lo];
+    int bi, bj;
+    tile_coords<SYM>(b - prefix[lo], g.M, g.N, BM, BN, bi, bj);
+    gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
+}
+
 // ------------------------------------------------------------ launching
 
 // Tile configurations: block tile, blocks per CU.
@@ -528,33 +566,30 @@ int tune_pick(int type, int M, int N, int K, int sym) { return pick_tile(type, M
 
 // ---------------------------------------------------------------- norms
 
-// Partial sums of squares in FP64: block b sums rows b, b + G, ... .
-__global__ __launch_bounds__(256) void fro_partial(const float *X, int64_t rows, int64_t cols, int64_t ld,
-                                                   double *part) {
+// Partial sums of squares in FP64 of one matrix: chunk b of nb sums rows
+// b, b + nb, ...
+__device__ __forceinline__ void fro_partial_body(const NormOp &op, int b, double *red) {
     double acc = 0.0;
-    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-        const float *p = X + r * ld;
-        for (int64_t c = threadIdx.x; c < cols; c += 256) {
+    for (int64_t r = b; r < op.rows; r += op.nparts) {
+        const float *p = op.X + r * op.ld;
+        for (int64_t c = threadIdx.x; c < op.cols; c += 256) {
             const double v = (double)p[c];
             acc += v * v;
         }
     }
-    __shared__ double red[256];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) op.part[b] = red[0];
 }
 
-// Fixed-order final reduction, then the derived scalars of `mode`.
-__global__ __launch_bounds__(256) void fro_final(const double *part, int nparts, Scalars *sc, int mode,
-                                                 double tau) {
-    __shared__ double red[256];
+// Fixed-order final reduction (deterministic), then the derived scalars.
+__device__ __forceinline__ void fro_final_body(const NormOp &op, double *red) {
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
+    for (int i = threadIdx.x; i < op.nparts; i += 256) acc += op.part[i];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -562,19 +597,20 @@ __global__ __launch_bounds__(256) void fro_final(const double *part, int nparts,
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
+    Scalars *sc = op.sc;
     const double nrm = sqrt(red[0]);
     sc->d[D_NORM] = nrm;
-    if (mode == NORM_INPUT) {
+    if (op.mode == NORM_INPUT) {
         sc->d[D_NU] = nrm;
         sc->f[F_NU] = (float)nrm;
         sc->f[F_INV_NU] = nrm > 0.0 ? (float)(1.0 / nrm) : 0.0f;
-        sc->d[D_SHIFT] = nrm > 0.0 ? (tau / nrm) * (tau / nrm) : 0.0;
-    } else if (mode == NORM_THETA_P || mode == NORM_THETA_S) {
+        sc->d[D_SHIFT] = nrm > 0.0 ? (op.tau / nrm) * (op.tau / nrm) : 0.0;
+    } else if (op.mode == NORM_THETA_P || op.mode == NORM_THETA_S) {
         // theta = sqrt(||M||_F) bounds the spectral radius of the iterate:
         // M = X^T X (or H^2) has eigenvalues mu_i >= 0 and
         // ||M||_F = sqrt(sum mu_i^2) >= mu_max = sigma_max^2.
         const double theta = sqrt(nrm);
-        const int base = mode == NORM_THETA_P ? F_P1 : F_S1;
+        const int base = op.mode == NORM_THETA_P ? F_P1 : F_S1;
         const double it = theta > 0.0 ? 1.0 / theta : 0.0;
         sc->f[base] = (float)it;
         sc->f[base + 1] = (float)(it * it);
@@ -582,151 +618,319 @@ __global__ __launch_bounds__(256) void fro_final(const double *part, int nparts,
     }
 }
 
-hipError_t launch_fro_norm(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials,
-                           Scalars *sc, int mode, double tau, hipStream_t st) {
-    int nb = (int)(rows < NORM_PARTIALS ? rows : NORM_PARTIALS);
-    if (nb < 1) nb = 1;
-    TraceScope tr(st, "fro_norm", 0.0, 4.0 * rows * cols);
-    hipLaunchKernelGGL(fro_partial, dim3(nb), dim3(256), 0, st, X, rows, cols, ld, partials);
-    hipLaunchKernelGGL(fro_final, dim3(1), dim3(256), 0, st, partials, nb, sc, mode, tau);
+__device__ __forceinline__ int find_group(const int *prefix, int n, int b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void fro_partial(NormOp op) {
+    __shared__ double red[256];
+    fro_partial_body(op, blockIdx.x, red);
+}
+__global__ __launch_bounds__(256) void fro_final(NormOp op) {
+    __shared__ double red[256];
+    fro_final_body(op, red);
+}
+__global__ __launch_bounds__(256) void fro_partial_grouped(const NormOp *ops, const int *prefix, int n) {
+    __shared__ double red[256];
+    const int p = find_group(prefix, n, blockIdx.x);
+    fro_partial_body(ops[p], blockIdx.x - prefix[p], red);
+}
+__global__ __launch_bounds__(256) void fro_final_grouped(const NormOp *ops) {
+    __shared__ double red[256];
+    fro_final_body(ops[blockIdx.x], red);
+}
+
+NormOp make_norm_op(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials, Scalars *sc, int mode,
+                    double tau) {
+    NormOp op;
+    op.X = X;
+    op.rows = rows;
+    op.cols = cols;
+    op.ld = ld;
+    op.part = partials;
+    op.nparts = (int)(rows < NORM_PARTIALS ? (rows < 1 ? 1 : rows) : NORM_PARTIALS);
+    op.sc = sc;
+    op.mode = mode;
+    op.tau = tau;
+    return op;
+}
+
+hipError_t launch_norm_op(const NormOp &op, hipStream_t st) {
+    TraceScope tr(st, "fro_norm", 0.0, 4.0 * op.rows * op.cols);
+    hipLaunchKernelGGL(fro_partial, dim3(op.nparts), dim3(256), 0, st, op);
+    hipLaunchKernelGGL(fro_final, dim3(1), dim3(256), 0, st, op);
     return hipGetLastError();
 }
 
-// ---------------------------------------------------- transpose and copies
+hipError_t launch_fro_norm(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials,
+                           Scalars *sc, int mode, double tau, hipStream_t st) {
+    return launch_norm_op(make_norm_op(X, rows, cols, ld, partials, sc, mode, tau), st);
+}
 
-// Y = s A (m x n) and YT = s A^T (n x m); either output may be NULL.
-// 64 x 64 tiles through LDS, 256 threads, 16 elements each.
-__global__ __launch_bounds__(256) void scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda,
-                                                       float *Y, int64_t ldy, float *YT, int64_t ldyt,
-                                                       const Scalars *sc, int i_scale) {
-    __shared__ float tile[64][65];
-    const float s = scal(sc, i_scale);
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+hipError_t launch_norm_grouped(const NormOp *ops, const int *prefix, int n, int total_blocks, double bytes,
+                               hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    TraceScope tr(st, "fro_norm_grouped", 0.0, bytes);
+    hipLaunchKernelGGL(fro_partial_grouped, dim3(total_blocks), dim3(256), 0, st, ops, prefix, n);
+    hipLaunchKernelGGL(fro_final_grouped, dim3(n), dim3(256), 0, st, ops);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- tile ops
+
+// 64 x 64 tiles through LDS, 256 threads, 16 elements each.  One kernel for
+// every elementwise pass of the method:
+//   TOP_SCALE_T  Y = s X, YT = s X^T (either may be NULL)
+//   TOP_SHIFT    Y = X - shift I, the diagonal in FP64 (shift from sc)
+//   TOP_SYMM     Y = s (X + X^T) / 2
+//   TOP_CONVERT  L = lowp(s X) or lowp(s X^T), s = scale [x sc->f[i_scale]]
+__device__ __forceinline__ void tile_op_body(const TileOp &op, int tile, float (*lds)[65]) {
+    const int ntc = (int)((op.cols + 63) / 64);
+    const int64_t r0 = (int64_t)(tile / ntc) * 64, c0 = (int64_t)(tile % ntc) * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const float s = op.scale * (op.sc && op.i_scale >= 0 ? op.sc->f[op.i_scale] : 1.0f);
+    if (op.kind == TOP_SYMM) {
+        for (int k = ty; k < 64; k += 4) {  // mirrored tile X[c0.., r0..]
+            const int64_t r = c0 + k, c = r0 + tx;
+            lds[k][tx] = (r < op.rows && c < op.cols) ? op.X[r * op.ldx + c] : 0.0f;
+        }
+        __syncthreads();
+        for (int k = ty; k < 64; k += 4) {
+            const int64_t r = r0 + k, c = c0 + tx;
+            if (r < op.rows && c < op.cols) op.Y[r * op.ldy + c] = 0.5f * s * (op.X[r * op.ldx + c] + lds[tx][k]);
+        }
+        return;
+    }
+    const bool need_t = (op.kind == TOP_SCALE_T && op.YT) || (op.kind == TOP_CONVERT && op.ltrans);
+    const double shift = op.kind == TOP_SHIFT ? op.sc->d[D_SHIFT] : 0.0;
     for (int k = ty; k < 64; k += 4) {
         const int64_t r = r0 + k, c = c0 + tx;
-        float v = 0.0f;
-        if (r < m && c < n) {
-            v = s * A[r * lda + c];
-            if (Y) Y[r * ldy + c] = v;
+        const bool in = r < op.rows && c < op.cols;
+        float v = in ? op.X[r * op.ldx + c] : 0.0f;
+        if (op.kind == TOP_SHIFT) {
+            if (in) op.Y[r * op.ldy + c] = (r == c) ? (float)((double)v - shift) : v;
+            continue;
         }
-        tile[k][tx] = v;
+        v *= s;
+        if (in) {
+            if (op.kind == TOP_SCALE_T && op.Y) op.Y[r * op.ldy + c] = v;
+            if (op.kind == TOP_CONVERT && !op.ltrans) {
+                if (op.ltype == OP_F32)
+                    ((float *)op.L)[r * op.ldl + c] = v;
+                else
+                    store_lp(op.L, op.ltype, r * op.ldl + c, v, op.lplane);
+            }
+        }
+        if (need_t) lds[k][tx] = v;
     }
-    if (!YT) return;
+    if (!need_t) return;
     __syncthreads();
     for (int k = ty; k < 64; k += 4) {
-        const int64_t c = c0 + k, r = r0 + tx;  // YT[c][r] = tile[r - r0][c - c0]
-        if (c < n && r < m) YT[c * ldyt + r] = tile[tx][k];
+        const int64_t c = c0 + k, r = r0 + tx;  // out[c][r] = X[r][c]
+        if (c >= op.cols || r >= op.rows) continue;
+        const float v = lds[tx][k];
+        if (op.kind == TOP_SCALE_T) {
+            op.YT[c * op.ldyt + r] = v;
+        } else if (op.ltype == OP_F32) {
+            ((float *)op.L)[c * op.ldl + r] = v;
+        } else {
+            store_lp(op.L, op.ltype, c * op.ldl + r, v, op.lplane);
+        }
     }
+}
+
+__global__ __launch_bounds__(256) void tile_op(TileOp op) {
+    __shared__ float lds[64][65];
+    tile_op_body(op, blockIdx.x, lds);
+}
+__global__ __launch_bounds__(256) void tile_op_grouped(const TileOp *ops, const int *prefix, int n) {
+    __shared__ float lds[64][65];
+    const int p = find_group(prefix, n, blockIdx.x);
+    tile_op_body(ops[p], blockIdx.x - prefix[p], lds);
+}
+
+int tile_op_tiles(const TileOp &op) { return (int)(((op.rows + 63) / 64) * ((op.cols + 63) / 64)); }
+
+double tile_op_bytes(const TileOp &op) {
+    const double e = (double)op.rows * op.cols;
+    switch (op.kind) {
+        case TOP_SCALE_T: return e * 4.0 * (1 + (op.Y != nullptr) + (op.YT != nullptr));
+        case TOP_SHIFT: return e * 8.0;
+        case TOP_SYMM: return e * 12.0;
+        default: return e * (4.0 + (op.ltype == OP_F32 ? 4 : op.ltype == OP_FP8 ? 1 : op.ltype == OP_BF16 ? 2 : 4));
+    }
+}
+
+static const char *kTileOpName[4] = {"scale_transpose", "shift_copy", "symmetrize_scale", "convert"};
+
+hipError_t launch_tile_op(const TileOp &op, hipStream_t st) {
+    const int n = tile_op_tiles(op);
+    if (n <= 0) return hipSuccess;
+    TraceScope tr(st, kTileOpName[op.kind], 0.0, tile_op_bytes(op));
+    hipLaunchKernelGGL(tile_op, dim3(n), dim3(256), 0, st, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_op_grouped(const TileOp *ops, const int *prefix, int n, int total, int kind, double bytes,
+                                  hipStream_t st) {
+    if (n <= 0 || total <= 0) return hipSuccess;
+    char name[48];
+    snprintf(name, sizeof name, "%s_grouped", kTileOpName[kind]);
+    TraceScope tr(st, trace_name(name), 0.0, bytes);
+    hipLaunchKernelGGL(tile_op_grouped, dim3(total), dim3(256), 0, st, ops, prefix, n);
+    return hipGetLastError();
+}
+
+static TileOp blank_op(int kind) {
+    TileOp op;
+    memset(&op, 0, sizeof op);
+    op.kind = kind;
+    op.scale = 1.0f;
+    op.i_scale = -1;
+    return op;
+}
+
+TileOp make_scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda, float *Y, int64_t ldy, float *YT,
+                            int64_t ldyt, const Scalars *sc, int i_scale) {
+    TileOp op = blank_op(TOP_SCALE_T);
+    op.X = A;
+    op.rows = m;
+    op.cols = n;
+    op.ldx = lda;
+    op.Y = Y;
+    op.ldy = ldy;
+    op.YT = YT;
+    op.ldyt = ldyt;
+    op.sc = sc;
+    op.i_scale = i_scale;
+    return op;
+}
+
+TileOp make_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc) {
+    TileOp op = blank_op(TOP_SHIFT);
+    op.X = T;
+    op.rows = op.cols = s;
+    op.ldx = ldt;
+    op.Y = H;
+    op.ldy = ldh;
+    op.sc = sc;
+    return op;
+}
+
+TileOp make_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, int64_t ldh, const Scalars *sc) {
+    TileOp op = blank_op(TOP_SYMM);
+    op.X = G;
+    op.rows = op.cols = n;
+    op.ldx = ldg;
+    op.Y = H;
+    op.ldy = ldh;
+    op.sc = sc;
+    op.i_scale = F_INV_NU;
+    return op;
+}
+
+TileOp make_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy, int type,
+                    float scale, int transpose, const Scalars *sc, int i_scale, int64_t plane) {
+    TileOp op = blank_op(TOP_CONVERT);
+    op.X = X;
+    op.rows = rows;
+    op.cols = cols;
+    op.ldx = ld;
+    op.L = Y;
+    op.ldl = ldy;
+    op.ltype = type;
+    op.ltrans = transpose;
+    op.lplane = plane;
+    op.scale = scale;
+    op.sc = sc;
+    op.i_scale = i_scale;
+    return op;
 }
 
 hipError_t launch_scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda, float *Y, int64_t ldy,
                                   float *YT, int64_t ldyt, const Scalars *sc, int i_scale, hipStream_t st) {
     if (m <= 0 || n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
-    TraceScope tr(st, "scale_transpose", 0.0, 4.0 * m * n * (1 + (Y != nullptr) + (YT != nullptr)));
-    hipLaunchKernelGGL(scale_transpose, grid, dim3(256), 0, st, A, m, n, lda, Y, ldy, YT, ldyt, sc, i_scale);
-    return hipGetLastError();
-}
-
-// H = T - shift I with the diagonal subtraction done in FP64
-// (shift = (tau/nu)^2 from the scalar block).
-__global__ __launch_bounds__(256) void shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh,
-                                                  const Scalars *sc) {
-    const double shift = sc->d[D_SHIFT];
-    for (int64_t r = blockIdx.x; r < s; r += gridDim.x) {
-        const float *src = T + r * ldt;
-        float *dst = H + r * ldh;
-        for (int64_t c = threadIdx.x; c < s; c += 256) {
-            float v = src[c];
-            if (c == r) v = (float)((double)v - shift);
-            dst[c] = v;
-        }
-    }
+    return launch_tile_op(make_scale_transpose(A, m, n, lda, Y, ldy, YT, ldyt, sc, i_scale), st);
 }
 
 hipError_t launch_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc,
                              hipStream_t st) {
     if (s <= 0) return hipSuccess;
-    const int nb = (int)(s < 2048 ? s : 2048);
-    TraceScope tr(st, "shift_copy", 0.0, 8.0 * s * s);
-    hipLaunchKernelGGL(shift_copy, dim3(nb), dim3(256), 0, st, T, s, ldt, H, ldh, sc);
-    return hipGetLastError();
-}
-
-// H = (G + G^T) / (2 nu), nu = ||G||_F from the scalar block.
-__global__ __launch_bounds__(256) void symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H,
-                                                        int64_t ldh, const Scalars *sc) {
-    __shared__ float tile[64][65];
-    const float s = 0.5f * sc->f[F_INV_NU];
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    // load the mirrored tile G[c0.., r0..]
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t r = c0 + k, c = r0 + tx;
-        tile[k][tx] = (r < n && c < n) ? G[r * ldg + c] : 0.0f;
-    }
-    __syncthreads();
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t r = r0 + k, c = c0 + tx;
-        if (r < n && c < n) H[r * ldh + c] = s * (G[r * ldg + c] + tile[tx][k]);
-    }
+    return launch_tile_op(make_shift_copy(T, s, ldt, H, ldh, sc), st);
 }
 
 hipError_t launch_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, int64_t ldh,
                                    const Scalars *sc, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n + 63) / 64));
-    TraceScope tr(st, "symmetrize_scale", 0.0, 12.0 * n * n);
-    hipLaunchKernelGGL(symmetrize_scale, grid, dim3(256), 0, st, G, n, ldg, H, ldh, sc);
-    return hipGetLastError();
-}
-
-// Y = round(scale * X) in `type`, optionally transposed.  64 x 64 tiles
-// through LDS so that both the reads and the writes are row-contiguous.
-__global__ __launch_bounds__(256) void convert_tile(const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y,
-                                                    int64_t ldy, int type, float scale0, int transpose,
-                                                    const Scalars *sc, int i_scale, int64_t plane) {
-    __shared__ float tile[64][65];
-    const float scale = scale0 * (sc ? scal(sc, i_scale) : 1.0f);
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t r = r0 + k, c = c0 + tx;
-        const float v = (r < rows && c < cols) ? scale * X[r * ldx + c] : 0.0f;
-        if (!transpose) {
-            if (r < rows && c < cols) {
-                if (type == OP_F32)
-                    ((float *)Y)[r * ldy + c] = v;
-                else
-                    store_lp(Y, type, r * ldy + c, v, plane);
-            }
-        } else {
-            tile[k][tx] = v;
-        }
-    }
-    if (!transpose) return;
-    __syncthreads();
-    for (int k = ty; k < 64; k += 4) {
-        const int64_t c = c0 + k, r = r0 + tx;  // Y[c][r] = X[r][c]
-        if (c < cols && r < rows) {
-            if (type == OP_F32)
-                ((float *)Y)[c * ldy + r] = tile[tx][k];
-            else
-                store_lp(Y, type, c * ldy + r, tile[tx][k], plane);
-        }
-    }
+    return launch_tile_op(make_symmetrize_scale(G, n, ldg, H, ldh, sc), st);
 }
 
 hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ldx, void *Y, int64_t ldy, int type,
                           float scale, int transpose, hipStream_t st, const Scalars *sc, int i_scale, int64_t plane) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
     if (type < 0 || type > 3) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
-    TraceScope tr(st, "convert", 0.0, (double)rows * cols * (4.0 + (type == OP_F32 ? 4 : type == OP_BF16 ? 2 : 1)));
-    hipLaunchKernelGGL(convert_tile, grid, dim3(256), 0, st, X, rows, cols, ldx, Y, ldy, type, scale, transpose, sc,
-                       i_scale, plane);
+    return launch_tile_op(make_convert(X, rows, cols, ldx, Y, ldy, type, scale, transpose, sc, i_scale, plane), st);
+}
+
+// ----------------------------------------------------------- grouped GEMM
+
+template <int ET, int BM, int OCC>
+static hipError_t grouped_cfg(const GemmArgs *args, const int *prefix, int n, int total, int sym, int two_a,
+                              double flops, hipStream_t st, const char *tag) {
+    char name[48];
+    snprintf(name, sizeof name, "%s_%s_%s_grouped", sym ? "syrk" : (two_a ? "gemm2" : "gemm"), kTypeTag[ET], tag);
+    TraceScope tr(st, trace_name(name), flops, 0.0);
+    if (sym)
+        hipLaunchKernelGGL((gemm_grouped<ET, BM, BM, OCC, false, true>), dim3(total), dim3(256), 0, st, args, prefix, n);
+    else if (two_a && ET == OP_F32)
+        hipLaunchKernelGGL((gemm_grouped<ET, BM, BM, OCC, ET == OP_F32, false>), dim3(total), dim3(256), 0, st, args,
+                           prefix, n);
+    else
+        hipLaunchKernelGGL((gemm_grouped<ET, BM, BM, OCC, false, false>), dim3(total), dim3(256), 0, st, args, prefix,
+                           n);
     return hipGetLastError();
+}
+
+template <int ET>
+static hipError_t grouped_type(const GemmArgs *args, const int *prefix, int n, int total, int tile, int sym, int two_a,
+                               double flops, hipStream_t st) {
+    switch (tile) {
+        case 1: return grouped_cfg<ET, 64, 4>(args, prefix, n, total, sym, two_a, flops, st, "64");
+        case 3: return grouped_cfg<ET, 192, 1>(args, prefix, n, total, sym, two_a, flops, st, "192");
+        case 4: return grouped_cfg<ET, 256, 1>(args, prefix, n, total, sym, two_a, flops, st, "256");
+        default: return grouped_cfg<ET, 128, 2>(args, prefix, n, total, sym, two_a, flops, st, "128");
+    }
+}
+
+hipError_t launch_gemm_grouped(const GemmArgs *args, const int *prefix, int n, int total, int op_type, int tile,
+                               int sym, int two_a, double flops, hipStream_t st) {
+    if (n <= 0 || total <= 0) return hipSuccess;
+    switch (op_type) {
+        case OP_F32: return grouped_type<OP_F32>(args, prefix, n, total, tile, sym, two_a, flops, st);
+        case OP_BF16: return grouped_type<OP_BF16>(args, prefix, n, total, tile, sym, two_a, flops, st);
+        case OP_FP8: return grouped_type<OP_FP8>(args, prefix, n, total, tile, sym, two_a, flops, st);
+        case OP_BF16X3: return grouped_type<OP_BF16X3>(args, prefix, n, total, tile, sym, two_a, flops, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Host helpers for building grouped launches.
+int gemm_pick_tile(const GemmArgs &g, int op_type) { return pick_tile(op_type, g.M, g.N, g.K, g.sym); }
+int gemm_tile_count(const GemmArgs &g, int tile) { return tile_count(g.M, g.N, g.sym, kTiles[tile].bm); }
+double gemm_model_us(const GemmArgs &g, int op_type, int tile) {
+    return model_time_us(op_type, g.M, g.N, g.K, g.sym, tile);
+}
+void gemm_prepare(GemmArgs &g) {
+    g.c_vec = g.C && ((uintptr_t)g.C & 15) == 0 && g.ldc % 4 == 0;
+    g.ct_vec = g.CT && ((uintptr_t)g.CT & 15) == 0 && g.ldct % 4 == 0;
 }
 
 }  // namespace psvt

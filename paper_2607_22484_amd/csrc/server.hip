@@ -1,0 +1,509 @@
+// Serving core: a request loop for soft-thresholding calls of mixed sizes,
+// with admission by an HBM budget and iteration-level continuous batching.
+//
+// Requests are admitted in arrival order while a slot is free and the
+// server's device memory pool (the HBM budget) has room for the request's
+// workspace; their iterates then live in that workspace until completion.
+// A worker thread runs ticks.  In one tick every active request advances
+// by up to `rounds` stages of its stage list; the stages of one round are
+// grouped by kind (products also by operand type and tile configuration)
+// into grouped launches, so requests at different points of their iteration
+// share launches and a request admitted during the run joins at the next
+// tick.  Each product tile is computed exactly as in a single call, so a
+// result does not depend on what it was batched with.  At most `depth` ticks
+// are in flight on the stream; a request completes when the event of the
+// tick that launched its last stage has passed, and its workspace returns to
+// the pool.
+//
+// With PSVT_SERVER_FAKE the same scheduler runs without a device: stages
+// complete immediately (for testing admission and scheduling on a CPU).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/psvt.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace psvt;
+
+namespace psvt {
+int plan_request(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, std::vector<Stage> &out,
+                 size_t *ws_bytes, bool check_dev);
+int set_error(int code, const char *msg);
+}  // namespace psvt
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// First-fit allocator over [0, size) in 256-byte units.
+class Pool {
+  public:
+    explicit Pool(size_t size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = align256(std::max<size_t>(bytes, 256));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(std::max<size_t>(bytes, 256));
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+
+  private:
+    std::map<size_t, size_t> free_;  // offset -> length
+    size_t used_ = 0, peak_ = 0;
+};
+
+enum { RQ_QUEUED = 0, RQ_RUNNING = 1, RQ_DONE = 2, RQ_FAILED = -1 };
+
+struct Request {
+    uint64_t ticket;
+    int op;
+    psvt_batch_item item;
+    size_t ws_bytes = 0, ws_off = 0;
+    std::vector<Stage> plan;
+    size_t cursor = 0;
+    int state = RQ_QUEUED;
+    int64_t finish_tick = -1;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+}  // namespace
+
+struct psvt_server {
+    bool fake = false;
+    size_t budget = 0;
+    int max_slots = 1, rounds = 3, depth = 3;
+    psvt_config cfg{};
+    std::vector<double> coeffs;
+    char *pool_dev = nullptr;
+    Pool *pool = nullptr;
+    int device = 0;
+
+    // descriptor ring: one segment per in-flight tick
+    static constexpr size_t kSegBytes = 1 << 20;
+    int nseg = 0;
+    char *ring_host = nullptr, *ring_dev = nullptr;
+    std::vector<hipEvent_t> seg_event;
+    std::vector<int64_t> seg_tick;
+    hipStream_t stream = nullptr;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;
+    std::unordered_map<uint64_t, Request *> all;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    int error = PSVT_OK;
+
+    // statistics
+    int64_t submitted = 0, completed = 0, failed = 0, ticks = 0, launches = 0;
+    std::vector<double> latency_ms, queue_ms;
+    double first_submit = -1, last_done = -1;
+};
+
+namespace {
+
+// Grouped launches of one round (stages with equal signatures).
+struct GroupKey {
+    int kind, dtype, sym, two_a, tile, tkind;
+    bool operator<(const GroupKey &o) const {
+        return std::tie(kind, dtype, sym, two_a, tile, tkind) < std::tie(o.kind, o.dtype, o.sym, o.two_a, o.tile, o.tkind);
+    }
+};
+
+int launch_round(psvt_server *s, std::vector<Request *> &reqs, int seg, size_t &seg_used) {
+    std::map<GroupKey, std::vector<Request *>> groups;
+    for (Request *r : reqs) {
+        const Stage &st = r->plan[r->cursor];
+        GroupKey k{st.kind, st.kind == ST_GEMM ? st.dtype : 0, st.kind == ST_GEMM ? st.g.sym : 0,
+                   st.kind == ST_GEMM ? (st.g.A2 != nullptr) : 0, st.kind == ST_GEMM ? gemm_pick_tile(st.g, st.dtype) : 0,
+                   st.kind == ST_TILE ? st.t.kind : 0};
+        groups[k].push_back(r);
+    }
+    char *hseg = s->ring_host + (size_t)seg * psvt_server::kSegBytes;
+    char *dseg = s->ring_dev + (size_t)seg * psvt_server::kSegBytes;
+    for (auto &kv : groups) {
+        const GroupKey &k = kv.first;
+        auto &rs = kv.second;
+        if (k.kind == ST_GEMM)  // largest first
+            std::stable_sort(rs.begin(), rs.end(), [&](Request *a, Request *b) {
+                return gemm_model_us(a->plan[a->cursor].g, k.dtype, k.tile) >
+                       gemm_model_us(b->plan[b->cursor].g, k.dtype, k.tile);
+            });
+        const size_t esz = k.kind == ST_GEMM ? sizeof(GemmArgs) : (k.kind == ST_NORM ? sizeof(NormOp) : sizeof(TileOp));
+        const size_t need = align256(esz * rs.size()) + align256(sizeof(int) * rs.size());
+        if (seg_used + need > psvt_server::kSegBytes) return set_error(PSVT_EINVAL, "server descriptor segment full");
+        char *hops = hseg + seg_used, *hpre = hops + align256(esz * rs.size());
+        const char *dops = dseg + seg_used, *dpre = dops + align256(esz * rs.size());
+        int total = 0;
+        double flops = 0.0, bytes = 0.0;
+        for (size_t i = 0; i < rs.size(); ++i) {
+            const Stage &st = rs[i]->plan[rs[i]->cursor];
+            ((int *)hpre)[i] = total;
+            if (k.kind == ST_GEMM) {
+                ((GemmArgs *)hops)[i] = st.g;
+                total += gemm_tile_count(st.g, k.tile);
+                flops += st.g.sym ? (double)st.g.M * (st.g.M + 1) * st.g.K : 2.0 * st.g.M * st.g.N * st.g.K;
+            } else if (k.kind == ST_NORM) {
+                ((NormOp *)hops)[i] = st.n;
+                total += st.n.nparts;
+                bytes += 4.0 * st.n.rows * st.n.cols;
+            } else {
+                ((TileOp *)hops)[i] = st.t;
+                total += tile_op_tiles(st.t);
+                bytes += tile_op_bytes(st.t);
+            }
+        }
+        seg_used += need;
+        s->launches += 1;
+        if (s->fake) continue;
+        hipError_t e = hipMemcpyAsync((void *)dops, hops, need, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) {
+            const int n = (int)rs.size();
+            if (k.kind == ST_GEMM)
+                e = launch_gemm_grouped((const GemmArgs *)dops, (const int *)dpre, n, total, k.dtype, k.tile, k.sym,
+                                        k.two_a, flops, s->stream);
+            else if (k.kind == ST_NORM)
+                e = launch_norm_grouped((const NormOp *)dops, (const int *)dpre, n, total, bytes, s->stream);
+            else
+                e = launch_tile_op_grouped((const TileOp *)dops, (const int *)dpre, n, total, k.tkind, bytes,
+                                           s->stream);
+        }
+        if (e != hipSuccess) return set_error(PSVT_EHIP, hipGetErrorString(e));
+    }
+    for (Request *r : reqs) r->cursor++;
+    return PSVT_OK;
+}
+
+void finish(psvt_server *s, Request *r, int state) {
+    r->state = state;
+    r->t_done = now_s();
+    if (s->pool) s->pool->release(r->ws_off, r->ws_bytes);
+    r->plan.clear();
+    r->plan.shrink_to_fit();
+    if (state == RQ_DONE) {
+        s->completed++;
+        s->latency_ms.push_back(1e3 * (r->t_done - r->t_submit));
+        s->queue_ms.push_back(1e3 * (r->t_admit - r->t_submit));
+        s->last_done = r->t_done;
+    } else {
+        s->failed++;
+    }
+}
+
+void worker_main(psvt_server *s) {
+    if (!s->fake) (void)hipSetDevice(s->device);
+    int64_t tick = 0;
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        // admission: arrival order, one slot and pool room per request
+        while (!s->queue.empty() && (int)s->active.size() < s->max_slots) {
+            Request *r = s->queue.front();
+            size_t off = 0;
+            if (!s->pool->alloc(r->ws_bytes, &off)) break;  // wait for memory (no overtaking)
+            r->ws_off = off;
+            r->plan.clear();
+            const int rc = plan_request(r->op, r->item, s->fake ? (void *)(uintptr_t)(4096 + off) : s->pool_dev + off,
+                                        &s->cfg, r->plan, &r->ws_bytes, !s->fake);
+            s->queue.pop_front();
+            r->t_admit = now_s();
+            if (rc != PSVT_OK) {
+                finish(s, r, RQ_FAILED);
+                s->cv_done.notify_all();
+                continue;
+            }
+            r->state = RQ_RUNNING;
+            s->active.push_back(r);
+        }
+        // completions
+        bool any_done = false;
+        for (size_t i = 0; i < s->active.size();) {
+            Request *r = s->active[i];
+            bool done = false;
+            if (r->finish_tick >= 0) {
+                if (s->fake) {
+                    done = true;
+                } else {
+                    const int seg = (int)(r->finish_tick % s->nseg);
+                    done = s->seg_tick[seg] != r->finish_tick || hipEventQuery(s->seg_event[seg]) == hipSuccess;
+                }
+            }
+            if (done) {
+                finish(s, r, RQ_DONE);
+                s->active[i] = s->active.back();
+                s->active.pop_back();
+                any_done = true;
+            } else {
+                ++i;
+            }
+        }
+        if (any_done) {
+            s->cv_done.notify_all();
+            continue;  // admit into the freed room first
+        }
+        std::vector<Request *> runnable;
+        for (Request *r : s->active)
+            if (r->cursor < r->plan.size()) runnable.push_back(r);
+        if (runnable.empty()) {
+            if (s->stop && s->queue.empty() && s->active.empty()) break;
+            // wait for arrivals or for in-flight ticks to finish
+            s->cv_work.wait_for(lk, std::chrono::microseconds(s->active.empty() ? 2000 : 50));
+            continue;
+        }
+        // one tick: reuse the oldest segment once its tick has finished
+        const int seg = (int)(tick % s->nseg);
+        if (!s->fake && s->seg_tick[seg] >= 0) {
+            hipEvent_t ev = s->seg_event[seg];
+            lk.unlock();
+            (void)hipEventSynchronize(ev);
+            lk.lock();
+        }
+        size_t seg_used = 0;
+        int rc = PSVT_OK;
+        for (int round = 0; round < s->rounds && rc == PSVT_OK; ++round) {
+            std::vector<Request *> rr;
+            for (Request *r : runnable)
+                if (r->cursor < r->plan.size()) rr.push_back(r);
+            if (rr.empty()) break;
+            rc = launch_round(s, rr, seg, seg_used);
+        }
+        if (!s->fake) {
+            (void)hipEventRecord(s->seg_event[seg], s->stream);
+            s->seg_tick[seg] = tick;
+        }
+        for (Request *r : runnable)
+            if (r->cursor >= r->plan.size() && r->finish_tick < 0) r->finish_tick = tick;
+        s->ticks++;
+        ++tick;
+        if (rc != PSVT_OK) {
+            s->error = rc;
+            for (Request *r : runnable) {
+                finish(s, r, RQ_FAILED);
+                s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+            }
+            s->cv_done.notify_all();
+        }
+    }
+}
+
+double percentile(std::vector<double> v, double q) {
+    if (v.empty()) return 0.0;
+    std::sort(v.begin(), v.end());
+    const double k = (v.size() - 1) * q;
+    const size_t lo = (size_t)k, hi = std::min(v.size() - 1, lo + 1);
+    return v[lo] + (v[hi] - v[lo]) * (k - lo);
+}
+
+}  // namespace
+
+extern "C" {
+
+int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config *cfg, uint32_t flags,
+                       psvt_server **out) {
+    if (!out) return set_error(PSVT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (budget_bytes < 4096 || max_slots < 1 || max_slots > 4096)
+        return set_error(PSVT_EINVAL, "bad budget or slot count");
+    if (flags & ~(uint32_t)PSVT_SERVER_FAKE) return set_error(PSVT_EINVAL, "unknown server flags");
+    psvt_server *s = new psvt_server();
+    s->fake = (flags & PSVT_SERVER_FAKE) != 0;
+    s->budget = budget_bytes;
+    s->max_slots = max_slots;
+    if (cfg) {
+        s->cfg = *cfg;
+        const int iters = cfg->iters ? cfg->iters : 20;
+        if (cfg->coeffs) {
+            s->coeffs.assign(cfg->coeffs, cfg->coeffs + 3 * iters);
+            s->cfg.coeffs = s->coeffs.data();
+        }
+    }
+    // descriptor ring: depth + 1 segments of 1 MiB
+    s->nseg = s->depth + 1;
+    s->seg_tick.assign(s->nseg, -1);
+    s->pool = new Pool(budget_bytes);
+    if (!s->fake) {
+        hipError_t e = hipGetDevice(&s->device);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->pool_dev, budget_bytes);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s->ring_host, psvt_server::kSegBytes * s->nseg, 0);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->ring_dev, psvt_server::kSegBytes * s->nseg);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        for (int i = 0; i < s->nseg && e == hipSuccess; ++i) {
+            hipEvent_t ev;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) s->seg_event.push_back(ev);
+        }
+        if (e != hipSuccess) {
+            psvt_server_destroy(s);
+            return set_error(PSVT_EHIP, hipGetErrorString(e));
+        }
+    } else {
+        s->ring_host = (char *)malloc(psvt_server::kSegBytes * s->nseg);
+        s->ring_dev = s->ring_host;
+    }
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return PSVT_OK;
+}
+
+int psvt_server_submit(psvt_server *s, int op, const psvt_batch_item *item, uint64_t *ticket) {
+    if (!s || !item || !ticket) return set_error(PSVT_EINVAL, "NULL argument");
+    if (op != PSVT_OP_SVT && op != PSVT_OP_RANK_R) return set_error(PSVT_EINVAL, "op must be svt or rank_r");
+    const psvt_batch_item &it = *item;
+    if (it.m < 1 || it.n < 1 || !it.A || !it.Y || it.lda < it.n || it.ldy < it.n || !(it.tau >= 0.0) ||
+        it.tau > 1e300)
+        return set_error(PSVT_EINVAL, "bad request");
+    Request *r = new Request();
+    r->op = op;
+    r->item = it;
+    std::vector<Stage> none;
+    int rc = plan_request(op, it, nullptr, &s->cfg, none, &r->ws_bytes, false);
+    if (rc != PSVT_OK) {
+        delete r;
+        return rc;
+    }
+    if (align256(r->ws_bytes) > s->budget) {
+        delete r;
+        return set_error(PSVT_EWORKSPACE, "request workspace exceeds the server's memory budget");
+    }
+    r->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            delete r;
+            return set_error(PSVT_EINVAL, "server is shutting down");
+        }
+        r->ticket = s->next_ticket++;
+        s->all[r->ticket] = r;
+        s->queue.push_back(r);
+        s->submitted++;
+        if (s->first_submit < 0) s->first_submit = r->t_submit;
+        *ticket = r->ticket;
+    }
+    s->cv_work.notify_one();
+    return PSVT_OK;
+}
+
+int psvt_server_poll(psvt_server *s, uint64_t ticket, int32_t *state) {
+    if (!s || !state) return set_error(PSVT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(PSVT_EINVAL, "unknown ticket");
+    *state = it->second->state;
+    return PSVT_OK;
+}
+
+int psvt_server_wait(psvt_server *s, uint64_t ticket, double timeout_s, int32_t *state) {
+    if (!s) return set_error(PSVT_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return set_error(PSVT_EINVAL, "unknown ticket");
+    Request *r = it->second;
+    const auto until = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+    while (r->state == RQ_QUEUED || r->state == RQ_RUNNING)
+        if (s->cv_done.wait_until(lk, until) == std::cv_status::timeout) break;
+    if (state) *state = r->state;
+    return PSVT_OK;
+}
+
+int psvt_server_drain(psvt_server *s, double timeout_s) {
+    if (!s) return set_error(PSVT_EINVAL, "NULL server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto until = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s);
+    while (!s->queue.empty() || !s->active.empty())
+        if (s->cv_done.wait_until(lk, until) == std::cv_status::timeout)
+            return set_error(PSVT_EINVAL, "drain timed out");
+    return s->error;
+}
+
+int psvt_server_stats(psvt_server *s, psvt_server_counters *st) {
+    if (!s || !st) return set_error(PSVT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(st, 0, sizeof *st);
+    st->submitted = s->submitted;
+    st->completed = s->completed;
+    st->failed = s->failed;
+    st->queued = (int64_t)s->queue.size();
+    st->active = (int64_t)s->active.size();
+    st->ticks = s->ticks;
+    st->launches = s->launches;
+    st->p50_ms = percentile(s->latency_ms, 0.5);
+    st->p99_ms = percentile(s->latency_ms, 0.99);
+    st->max_ms = s->latency_ms.empty() ? 0.0 : *std::max_element(s->latency_ms.begin(), s->latency_ms.end());
+    st->queue_p99_ms = percentile(s->queue_ms, 0.99);
+    const double span = s->last_done - s->first_submit;
+    st->matrices_per_s = (s->completed > 0 && span > 0) ? s->completed / span : 0.0;
+    st->budget_bytes = s->budget;
+    st->peak_bytes = s->pool->peak();
+    return PSVT_OK;
+}
+
+int psvt_server_destroy(psvt_server *s) {
+    if (!s) return PSVT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    if (!s->fake) {
+        if (s->stream) (void)hipStreamSynchronize(s->stream);
+        for (hipEvent_t e : s->seg_event) (void)hipEventDestroy(e);
+        if (s->stream) (void)hipStreamDestroy(s->stream);
+        if (s->ring_dev) (void)hipFree(s->ring_dev);
+        if (s->ring_host) (void)hipHostFree(s->ring_host);
+        if (s->pool_dev) (void)hipFree(s->pool_dev);
+    } else {
+        free(s->ring_host);
+    }
+    for (auto &kv : s->all) delete kv.second;
+    delete s->pool;
+    delete s;
+    return PSVT_OK;
+}
+
+}  // extern "C"

@@ -147,3 +147,20 @@ def test_tune_pick_model():
     assert lib.psvt_tune_pick(7, 5, 5, 5, 0) == psvt.PSVT_EINVAL
     assert lib.psvt_tune_force_tile(9) == psvt.PSVT_EINVAL
     assert lib.psvt_tune_set(0, 1, 0, 0.0, 1.0) == psvt.PSVT_EINVAL
+
+
+def test_batch_validation():
+    lib = psvt.load()
+    items = (psvt.BatchItem * 2)()
+    items[0] = psvt.BatchItem(1 << 40, 1 << 41, 8, 4, 4, 4, 0.5)
+    items[1] = psvt.BatchItem(1 << 40, 1 << 41, 8, 4, 3, 4, 0.5)   # lda < n
+    out = ctypes.c_size_t(0)
+    assert lib.psvt_batch_workspace_bytes(0, items, 2, None, ctypes.byref(out)) == psvt.PSVT_EINVAL
+    assert lib.psvt_batch_workspace_bytes(0, items, 1, None, ctypes.byref(out)) == psvt.PSVT_OK
+    assert out.value == psvt.workspace_bytes(psvt.OP_SVT, 8, 4)
+    assert lib.psvt_batch_workspace_bytes(1, items, 1, None, ctypes.byref(out)) == psvt.PSVT_EINVAL  # polar
+    assert lib.psvt_batch_workspace_bytes(0, items, 0, None, ctypes.byref(out)) == psvt.PSVT_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.psvt_batch_create(0, items, 1, None, 1 << 30, None, ctypes.byref(h)) == psvt.PSVT_EWORKSPACE
+    assert lib.psvt_batch_run(None, None) == psvt.PSVT_EINVAL
+    assert lib.psvt_batch_destroy(None) == psvt.PSVT_OK

@@ -1,0 +1,104 @@
+"""Serving scheduler on the CPU (fake executor: stages complete at once).
+Checks admission order, the memory budget, slot limits, failure handling and
+statistics without a device.  Device pointers are fake and never touched."""
+import time
+
+import pytest
+
+import paper_2607_22484_amd as psvt
+
+FAKE_A = 1 << 40
+FAKE_Y = 1 << 41
+
+
+def submit(srv, m, n, tau=0.1):
+    return srv.submit_ptr(FAKE_A, FAKE_Y, m, n, n, n, tau)
+
+
+def test_fake_server_completes_everything():
+    srv = psvt.Server(budget_bytes=1 << 30, max_slots=8, fake=True)
+    tickets = [submit(srv, 64 + 16 * i, 48 + 8 * i) for i in range(40)]
+    srv.drain(timeout=30)
+    for t in tickets:
+        assert srv.poll(t) == psvt.RQ_DONE
+    st = srv.stats()
+    assert st["submitted"] == 40 and st["completed"] == 40 and st["failed"] == 0
+    assert st["queued"] == 0 and st["active"] == 0
+    assert st["p99_ms"] >= st["p50_ms"] >= 0.0
+    assert st["ticks"] > 0 and st["launches"] > 0
+    srv.close()
+
+
+def test_budget_limits_concurrency():
+    """With room for exactly two requests at a time, peak pool use never
+    exceeds the budget and every request still completes."""
+    need = psvt.workspace_bytes(psvt.OP_SVT, 256, 256)
+    budget = 2 * ((need + 255) // 256 * 256) + 1024
+    srv = psvt.Server(budget_bytes=budget, max_slots=16, fake=True)
+    tickets = [submit(srv, 256, 256) for _ in range(10)]
+    srv.drain(timeout=30)
+    st = srv.stats()
+    assert st["completed"] == 10
+    assert st["peak_bytes"] <= budget
+    assert st["peak_bytes"] >= 2 * need
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in tickets)
+    srv.close()
+
+
+def test_request_larger_than_budget_is_rejected():
+    srv = psvt.Server(budget_bytes=1 << 20, max_slots=4, fake=True)
+    with pytest.raises(psvt.PsvtError) as e:
+        submit(srv, 4096, 4096)
+    assert e.value.code == psvt.PSVT_EWORKSPACE
+    t = submit(srv, 32, 32)  # a small one still fits
+    assert srv.wait(t, timeout=10) == psvt.RQ_DONE
+    srv.close()
+
+
+def test_bad_requests_and_arguments():
+    srv = psvt.Server(budget_bytes=1 << 26, max_slots=2, fake=True)
+    for m, n, tau in [(0, 5, 0.1), (5, 0, 0.1), (8, 8, -1.0), (8, 8, float("nan"))]:
+        with pytest.raises(psvt.PsvtError):
+            srv.submit_ptr(FAKE_A, FAKE_Y, m, n, max(n, 1), max(n, 1), tau)
+    with pytest.raises(psvt.PsvtError):
+        srv.poll(12345)
+    srv.close()
+    lib = psvt.load()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lib.psvt_server_create(100, 4, None, psvt.SERVER_FAKE, ctypes.byref(h)) == psvt.PSVT_EINVAL
+    assert lib.psvt_server_create(1 << 20, 0, None, psvt.SERVER_FAKE, ctypes.byref(h)) == psvt.PSVT_EINVAL
+    assert lib.psvt_server_create(1 << 20, 4, None, 0x80, ctypes.byref(h)) == psvt.PSVT_EINVAL
+
+
+def test_fifo_admission_no_overtaking():
+    """A large request at the head of the queue is not overtaken by smaller
+    ones that would fit: admission is in arrival order."""
+    big = psvt.workspace_bytes(psvt.OP_SVT, 512, 512)
+    small = psvt.workspace_bytes(psvt.OP_SVT, 32, 32)
+    budget = (big + 255) // 256 * 256 + 2 * ((small + 255) // 256 * 256)
+    srv = psvt.Server(budget_bytes=budget, max_slots=8, fake=True)
+    ts = [submit(srv, 32, 32), submit(srv, 512, 512), submit(srv, 32, 32), submit(srv, 32, 32)]
+    srv.drain(timeout=30)
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in ts)
+    assert srv.stats()["peak_bytes"] <= budget
+    srv.close()
+
+
+def test_threads_submitting_concurrently():
+    import threading
+    srv = psvt.Server(budget_bytes=1 << 30, max_slots=32, fake=True)
+    out = []
+
+    def client(k):
+        for i in range(25):
+            out.append(submit(srv, 32 + k, 40 + i))
+    th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    srv.drain(timeout=30)
+    assert len(set(out)) == 100
+    assert srv.stats()["completed"] == 100
+    srv.close()
