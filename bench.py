@@ -82,6 +82,115 @@ def cpu_baseline_leg(problems, results, n_sample):
     return cpu, errs
 
 
+def time_calls(torch, fn, reps):
+    """Average device time of fn() over reps calls (events on the current stream)."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def precision_leg(psvt, torch, dev, check_oracle):
+    """Precision form: BF16 operand iterations (18) + 2 FP32, on rank-200
+    signal + noise, 8192 x 4096 and 4096 x 8192 (left-sided)."""
+    from paper_2607_22484_amd import inputs
+    out = {}
+    for (m, n) in [(8192, 4096), (4096, 8192)]:
+        pb = inputs.noisy_lowrank(m, n, rank=200, idx=0 if m > n else 1, norm_iters=40)
+        A = torch.from_numpy(pb.A).to(dev)
+        Y = torch.empty_like(A)
+        row = {}
+        for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18))]:
+            cfg, _ = psvt.make_config(iters=20, **kw)
+            ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, m, n, cfg), dtype=torch.uint8, device=dev)
+            ms = time_calls(torch, lambda: psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw), 3)
+            psvt.trace_begin()
+            psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw)
+            torch.cuda.synchronize()
+            tr = psvt.trace_end()
+            mfma = {}
+            for t in tr:
+                if t["flops"]:
+                    d = t["name"].split("_")[1]
+                    a = mfma.setdefault(d, [0.0, 0.0])
+                    a[0] += t["flops"] * (3 if d == "bf16x3" else 1)
+                    a[1] += t["total_ms"]
+            peak = {"f32": 157.3, "bf16": 2516.6, "bf16x3": 2516.6, "fp8": 5033.2}
+            row[name] = {"ms": ms, "matrices_per_s": 1e3 / ms,
+                         "useful_tflops": useful_flops(m, n, 20) / (ms * 1e-3) / 1e12,
+                         "mfma_util_by_dtype": {d: (f / (t * 1e-3) / 1e12) / peak[d] for d, (f, t) in mfma.items()}}
+            if check_oracle and m > n:
+                import oracle
+                ref = oracle.svt_gapped(pb.A, pb.tau, k=256)
+                row[name]["rel_err"] = oracle.rel_fro_err(Y.cpu().numpy().astype(np.float64), ref)
+        out["%dx%d" % (m, n)] = row
+    return out
+
+
+def batched_leg(psvt, torch, dev, check_oracle, count=512):
+    """Batched form: 512 matrices, m, n log-uniform in [128, 2048], one graph
+    launch per batch."""
+    from paper_2607_22484_amd import inputs
+    pbs = inputs.batch_cases(count=count)
+    As = [torch.from_numpy(p.A).to(dev) for p in pbs]
+    taus = [p.tau for p in pbs]
+    out = {"matrices": count}
+    for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)), ("bf16_splitP", dict(n_bf16=18, flags=2))]:
+        b = psvt.Batch(As, taus, iters=20, **kw)
+        nl, fl = b.stats()
+        ms = time_calls(torch, b.run_graph, 3)
+        row = {"ms_per_batch": ms, "matrices_per_s": count / (ms * 1e-3), "useful_tflops": fl / (ms * 1e-3) / 1e12,
+               "launches_in_graph": nl}
+        if check_oracle:
+            import oracle
+            worst = 0.0
+            for p, Y in zip(pbs, b.Ys):
+                ref = oracle.svt_from_svd(p.U, p.sigma, p.V, p.tau)
+                worst = max(worst, oracle.rel_fro_err(Y.cpu().numpy().astype(np.float64), ref))
+            row["worst_rel_err"] = worst
+        out[name] = row
+        b.close()
+    return out
+
+
+def serving_leg(psvt, torch, dev, rates=(200, 1000, 5000), count=300):
+    """Serving form: Poisson arrivals, sizes 256..4096 square and 2:1, rank
+    r in {16, 64, 256} + noise, 6 FP8 + 12 BF16 + 2 FP32 iterations."""
+    from paper_2607_22484_amd import inputs
+    g = torch.Generator(device=dev)
+    g.manual_seed(2607)
+    reqs = []
+    for (m, n, r) in inputs.serve_shapes(count, idx=0):
+        U = torch.linalg.qr(torch.randn(m, r, device=dev, generator=g))[0]
+        V = torch.linalg.qr(torch.randn(n, r, device=dev, generator=g))[0]
+        s = 1.0 + 9.0 * torch.rand(r, device=dev, generator=g)
+        A = ((U * s) @ V.T + torch.randn(m, n, device=dev, generator=g) * (0.01 / math.sqrt(n))).contiguous()
+        reqs.append((A, 2 * 0.01 * (math.sqrt(m) + math.sqrt(n)) / math.sqrt(n)))
+    torch.cuda.synchronize()
+    out = {}
+    for rate in rates:
+        srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, iters=20, n_fp8=6, n_bf16=12)
+        gaps = np.random.default_rng(rate).exponential(1.0 / rate, size=len(reqs))
+        t = time.perf_counter()
+        for (A, tau), gp in zip(reqs, gaps):
+            t += gp
+            while time.perf_counter() < t:
+                pass
+            srv.submit(A, tau)
+        srv.drain(timeout=600)
+        st = srv.stats()
+        out["%d_per_s" % rate] = {"completed": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                  "matrices_per_s": st["matrices_per_s"], "queue_p99_ms": st["queue_p99_ms"],
+                                  "peak_pool_gib": st["peak_bytes"] / 2 ** 30}
+        srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +200,7 @@ def main():
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (matrices are independent; "
@@ -192,6 +302,19 @@ def main():
         cpu, errs = cpu_baseline_leg(problems, res, args.cpu_sample)
         out["cpu_baseline"] = cpu
         out["accuracy"] = errs
+        out["rel_err_max"] = max(e["rel_err_bound_fp32_input"] for e in errs.values())
+    if not args.no_forms:
+        del A, Y, ws
+        torch.cuda.empty_cache()
+        forms = {}
+        print("[bench] precision form ...", file=sys.stderr, flush=True)
+        forms["precision"] = precision_leg(psvt, torch, dev, not args.no_cpu)
+        print("[bench] batched form ...", file=sys.stderr, flush=True)
+        forms["batched"] = batched_leg(psvt, torch, dev, not args.no_cpu)
+        torch.cuda.empty_cache()
+        print("[bench] serving form ...", file=sys.stderr, flush=True)
+        forms["serving"] = serving_leg(psvt, torch, dev)
+        out["forms"] = forms
     print(json.dumps(out), flush=True)
 
 

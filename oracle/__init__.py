@@ -22,6 +22,9 @@ by the one-sided Jacobi routine in ``jacobi.c`` (FP64):
                           tau strictly between sigma_{r+1} and sigma_r).
 * ``svt_from_svd``     -- Eq. (1) for factors already known (constructed
                           spectra): no SVD is computed.
+* ``svt_gapped``       -- Eq. (1) for large low-rank-plus-noise inputs, by the
+                          Jacobi SVD of a compressed matrix whose range holds
+                          every singular vector above tau (checked).
 
 Inputs are widened to float64 before anything else; callers hand in exactly
 the FP32 matrix the GPU sees.
@@ -134,6 +137,39 @@ def rank_r(A, tau, nthreads: int = 0):
     U, s, V = svd(A, nthreads)
     keep = np.where(s > tau, s, 0.0)
     return (U * keep) @ V.T
+
+
+def svt_gapped(A, tau, k, power_iters=6, seed=0, nthreads: int = 0):
+    """Eq. (1) for a large matrix whose singular values above tau are few and
+    separated by a wide gap from the rest (low-rank signal plus noise, tau =
+    2 ||N||_2), computed on a compressed matrix:
+
+      Q = orthonormal basis of (A A^T)^q A Omega  (Omega: n x k Gaussian),
+      B = Q^T A (k x n),  A_tau = Q (B)_tau  with (B)_tau by the Jacobi SVD.
+
+    Exact when range(Q) contains the left singular vectors of every
+    sigma > tau and the rest of A, (I - Q Q^T) A, has spectral norm <= tau;
+    the power steps make the first hold to working precision for a gapped
+    spectrum, and the second is checked (RuntimeError otherwise).  k must
+    exceed the number of singular values above tau."""
+    A = np.asarray(A, np.float64)
+    m, n = A.shape
+    if m < n:
+        return svt_gapped(A.T, tau, k, power_iters, seed, nthreads).T
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(A @ rng.standard_normal((n, k)))
+    for _ in range(power_iters):
+        Q, _ = np.linalg.qr(A @ (A.T @ Q))
+    B = Q.T @ A
+    R = A - Q @ B
+    x = rng.standard_normal(n)
+    for _ in range(50):  # ||R||_2 by power iteration (an underestimate: pad 5%)
+        x = R.T @ (R @ x)
+        x /= np.linalg.norm(x)
+    rnorm = float(np.linalg.norm(R @ x))
+    if rnorm * 1.05 > tau:
+        raise RuntimeError("residual %.3g not below tau %.3g: increase k" % (rnorm, tau))
+    return Q @ svt(B, tau, nthreads)
 
 
 def rel_fro_err(approx, exact, A=None):

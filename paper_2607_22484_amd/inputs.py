@@ -150,7 +150,7 @@ def noise_spectral_norm(N: np.ndarray, iters: int = 200, seed: int = 0) -> float
 
 
 def noisy_lowrank(m: int, n: int, rank: int = 200, idx: int = 0, noise: float = 0.01,
-                  sig_lo: float = 1.0, sig_hi: float = 10.0, cfg: int = CFG_NOISY) -> Problem:
+                  sig_lo: float = 1.0, sig_hi: float = 10.0, cfg: int = CFG_NOISY, norm_iters: int = 200) -> Problem:
     """Rank-``rank`` Haar signal with sigma ~ U[sig_lo, sig_hi] plus i.i.d.
     N(0, (noise/sqrt(n))^2), n = column count; tau = 2 ||N||_2."""
     rng = rng_for(cfg, idx)
@@ -159,7 +159,7 @@ def noisy_lowrank(m: int, n: int, rank: int = 200, idx: int = 0, noise: float = 
     sig = np.sort(rng.uniform(sig_lo, sig_hi, size=rank))[::-1]
     N = rng.standard_normal((m, n)) * (noise / math.sqrt(n))
     A64 = (U * sig) @ V.T + N
-    tau = 2.0 * noise_spectral_norm(N)
+    tau = 2.0 * noise_spectral_norm(N, iters=norm_iters)
     return Problem(A=A64.astype(np.float32), tau=tau, A64=A64, rank=rank, name="noisy_%dx%d_r%d" % (m, n, rank))
 
 

@@ -302,3 +302,14 @@ def test_empty_and_vector_shapes():
     a = np.array([[3.0], [4.0]])
     np.testing.assert_allclose(oracle.svt(a, 1.0), a * (4.0 / 5.0), atol=1e-15)
     np.testing.assert_allclose(oracle.svt(a.T, 1.0), a.T * (4.0 / 5.0), atol=1e-15)
+
+
+def test_svt_gapped_matches_full_jacobi():
+    """The compressed route for gapped low-rank + noise inputs equals the
+    full Jacobi oracle (it is the same Eq. (1) on an exact invariant subspace)."""
+    pb = inputs.noisy_lowrank(300, 160, rank=12, idx=5, cfg=inputs.CFG_TEST)
+    full = oracle.svt(pb.A, pb.tau)
+    assert relerr(oracle.svt_gapped(pb.A, pb.tau, k=32), full) < 1e-11
+    assert relerr(oracle.svt_gapped(pb.A.T, pb.tau, k=32), full.T) < 1e-11
+    with pytest.raises(RuntimeError):
+        oracle.svt_gapped(pb.A, pb.tau * 1e-3, k=8)   # k too small for this tau
