@@ -43,6 +43,49 @@ def useful_flops(m, n, iters, with_p=True):
     return float(f)
 
 
+def kernel_source_sha():
+    """Hash of the MFMA tile kernel's sources: a stored traffic figure is
+    reported only while it matches the kernel that was measured."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2607_22484_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("device.h", "tile.h", "kernels.h", "gemm_f32.hip", "gemm_bf16.hip", "gemm_fp8.hip", "gemm_bf16x3.hip"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the PMC summaries under
+    profiles/ (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy kernel's
+    reading), or None when absent or taken from other kernel sources."""
+    d = os.path.join(ROOT, "profiles")
+    sha = kernel_source_sha()
+    if not os.path.isdir(d):
+        return None
+    for f in sorted(os.listdir(d)):
+        if not f.startswith("traffic_"):
+            continue
+        with open(os.path.join(d, f)) as fh:
+            for line in fh:
+                if not line.startswith("traffic "):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("kernel") == kernel and kv.get("source_sha") == sha:
+                    return float(kv["traffic_bytes"])
+    return None
+
+
+def calibration_copy(torch, dev, nbytes=1 << 30):
+    """One plain elementwise pass (read nbytes, write nbytes) whose PMC
+    FETCH_SIZE / WRITE_SIZE readings scale the kernel's counters to bytes."""
+    x = torch.ones(nbytes // 4, device=dev)
+    y = torch.empty_like(x)
+    torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -201,6 +244,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (matrices are independent; "
@@ -213,6 +258,8 @@ def main():
 
     psvt.load()
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        calibration_copy(torch, dev)
     n = args.n
     quantiles = (0.1, 0.5, 0.9)
     t_gen = time.perf_counter()
@@ -265,7 +312,8 @@ def main():
         "bound": "mfma", "kernel": dom["name"], "launches": dom["launches"], "avg_launch_ms": dom_avg_ms,
         "flops_per_launch": dom["flops"] / dom["launches"],
         "achieved": dom_tflops, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-        "frac": dom_tflops / PEAK_TFLOPS["f32"], "traffic": None,
+        "frac": dom_tflops / PEAK_TFLOPS["f32"], "traffic": stored_traffic(dom["name"]),
+        "kernel_source_sha": kernel_source_sha(),
     }
     kernels = [{"name": t["name"], "launches": t["launches"], "ms_per_step": t["total_ms"] / args.steps,
                 "tflops": (t["flops"] / (t["total_ms"] * 1e-3) / 1e12) if t["flops"] else None,

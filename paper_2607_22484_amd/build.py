@@ -7,12 +7,14 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpsvt.so")
-SOURCES = ["api.hip", "kernels.hip", "trace.hip", "batch.hip", "server.hip"]
+SOURCES = ["gemm_f32.hip", "gemm_bf16x3.hip", "gemm_bf16.hip", "gemm_fp8.hip", "kernels.hip", "api.hip",
+           "trace.hip", "batch.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled: the compiler must not form
@@ -24,15 +26,21 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel: the per-operand-type tile units
+    dominate) and link ``libpsvt.so``."""
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
+    objs = [os.path.join(CSRC, src.replace(".hip", ".o")) for src in SOURCES]
+
+    def one(pair):
+        src, obj = pair
         cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(jobs) as ex:
+        list(ex.map(one, zip(SOURCES, objs)))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -62,6 +62,7 @@ struct GemmArgs {
     const Scalars *sc;
     int sym;
     int c_vec;       // C may take 16-byte stores (aligned, ldc % 4 == 0)
+    int direct;      // operand tiles by direct-to-LDS buffer loads (set by gemm_prepare)
     int ct_vec;      // CT may take 16-byte stores
     int lp_type;     // OpType of Clp/CTlp
     int64_t a_plane, b_plane;  // OP_BF16X3 operands: elements from the hi to the lo plane
@@ -134,7 +135,15 @@ hipError_t launch_gemm_grouped(const GemmArgs *args, const int *prefix, int n, i
 int gemm_pick_tile(const GemmArgs &g, int op_type);
 int gemm_tile_count(const GemmArgs &g, int tile);
 double gemm_model_us(const GemmArgs &g, int op_type, int tile);
-void gemm_prepare(GemmArgs &g);
+void gemm_prepare(GemmArgs &g, int op_type);
+// Raw launches of tile configuration `tile` (1..4 = 64/128/192/256) for
+// operand type ET (defined in tile.h, instantiated in gemm_<type>.hip); the
+// arguments must have gone through gemm_prepare.
+template <int ET>
+hipError_t gemm_launch(const GemmArgs &g, int tile, int nblocks, hipStream_t st);
+template <int ET>
+hipError_t gemm_launch_grouped(const GemmArgs *args, const int *prefix, int n, int total, int tile, int sym,
+                               int two_a, hipStream_t st);
 
 // modes for launch_fro_norm
 enum NormMode {

@@ -32,7 +32,7 @@ struct Exec {
             s.kind = ST_GEMM;
             s.dtype = dt;
             s.g = g;
-            gemm_prepare(s.g);
+            gemm_prepare(s.g, dt);
             s.what = what;
             rec->push_back(s);
             return hipSuccess;

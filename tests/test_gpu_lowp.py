@@ -79,7 +79,8 @@ def quantize(torch, dev, A, dtype, scale):
 
 @pytest.mark.parametrize("dtype", [1, 2])
 @pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
-@pytest.mark.parametrize("M,N,K,sym", [(200, 136, 256, False), (250, 250, 192, True), (64, 70, 100, False)])
+@pytest.mark.parametrize("M,N,K,sym", [(200, 136, 256, False), (250, 250, 192, True), (64, 70, 100, False),
+                                       (130, 300, 384, False)])
 def test_lowp_gemm_matches_fp64(gpu_lib, tdev, dtype, tile, M, N, K, sym):
     torch, dev = tdev
     _announce("lowp gemm dtype=%d tile=%d %dx%dx%d sym=%s" % (dtype, tile, M, N, K, sym))
@@ -109,7 +110,8 @@ def test_lowp_gemm_matches_fp64(gpu_lib, tdev, dtype, tile, M, N, K, sym):
 
 
 @pytest.mark.parametrize("tile", [0, 2, 4])
-@pytest.mark.parametrize("M,N,K,sym", [(200, 136, 200, False), (250, 250, 130, True)])
+@pytest.mark.parametrize("M,N,K,sym", [(200, 136, 200, False), (250, 250, 130, True), (200, 136, 256, False),
+                                       (250, 250, 192, True)])
 def test_split_bf16_gemm(gpu_lib, tdev, tile, M, N, K, sym):
     """Split bf16: x = hi + lo, product hi.hi + hi.lo + lo.hi, accurate to
     about 2^-16 relative (the dropped lo.lo term) plus FP32 accumulation."""

@@ -277,7 +277,10 @@ def test_square_4096_rank256(gpu_lib, torch_dev):
 # ------------------------------------------------ every tile configuration
 
 @pytest.mark.parametrize("tile", [1, 2, 3, 4])
-@pytest.mark.parametrize("M,N,K,sym", [(200, 328, 132, False), (450, 450, 300, True), (513, 260, 68, False)])
+# k extents that are (256, 320) and are not (132, 300, 68) whole 32-float
+# k-tiles: the direct-to-LDS and the register-staged tile bodies
+@pytest.mark.parametrize("M,N,K,sym", [(200, 328, 132, False), (450, 450, 300, True), (513, 260, 68, False),
+                                       (330, 200, 256, False), (450, 450, 320, True)])
 def test_gemm_every_tile(gpu_lib, torch_dev, tile, M, N, K, sym):
     torch, dev = torch_dev
     _announce("gemm tile=%d %dx%dx%d sym=%s" % (tile, M, N, K, sym))
