@@ -198,6 +198,17 @@ def batched_leg(psvt, torch, dev, check_oracle, count=512):
             row["worst_rel_err"] = worst
         out[name] = row
         b.close()
+    # the plain FP32 form on the same matrices: one matrix per launch sequence
+    cfg, _ = psvt.make_config(iters=20)
+    ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, p.shape[0], p.shape[1], cfg) for p in pbs),
+                     dtype=torch.uint8, device=dev)
+    Ys = [torch.empty_like(a) for a in As]
+
+    def single():
+        for a, y, t in zip(As, Ys, taus):
+            psvt.svt(a, t, iters=20, out=y, ws=ws)
+    ms = time_calls(torch, single, 1)
+    out["fp32_single_calls"] = {"ms_per_batch": ms, "matrices_per_s": count / (ms * 1e-3)}
     return out
 
 
@@ -216,6 +227,19 @@ def serving_leg(psvt, torch, dev, rates=(200, 1000, 5000), count=300):
         reqs.append((A, 2 * 0.01 * (math.sqrt(m) + math.sqrt(n)) / math.sqrt(n)))
     torch.cuda.synchronize()
     out = {}
+    # the plain FP32 form on the first 100 requests, one matrix per launch sequence
+    sample = reqs[:100]
+    cfg, _ = psvt.make_config(iters=20)
+    ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, A.shape[0], A.shape[1], cfg) for A, _ in sample),
+                     dtype=torch.uint8, device=dev)
+    Ys = [torch.empty_like(A) for A, _ in sample]
+
+    def single():
+        for (A, tau), Y in zip(sample, Ys):
+            psvt.svt(A, tau, iters=20, out=Y, ws=ws)
+    ms = time_calls(torch, single, 1)
+    out["fp32_single_calls"] = {"requests": len(sample), "matrices_per_s": len(sample) / (ms * 1e-3)}
+    del ws, Ys
     for rate in rates:
         srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, iters=20, n_fp8=6, n_bf16=12)
         gaps = np.random.default_rng(rate).exponential(1.0 / rate, size=len(reqs))

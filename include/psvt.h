@@ -241,11 +241,12 @@ int psvt_trace_begin(void);
 int psvt_trace_end(psvt_trace_stat *out, int max_entries, int *n_entries);
 
 /* Tile configurations of the MFMA kernels.  Ids: 1 = 64x64 tiles (4 blocks
- * per CU), 2 = 128x128 (2 per CU), 3 = 192x192 (1 per CU), 4 = 256x256
- * (1 per CU).  Each product picks the configuration with the smallest
+ * per CU; 2 for split bf16), 2 = 128x128 (2 per CU; 1 for split bf16),
+ * 3 = 192x192 (1 per CU), 4 = 256x256 (1 per CU).  Each product picks the configuration with the smallest
  * modelled time
  *     (most tiles on one CU) x (overhead + tile flops / (eff x CU rate)),
- * with (eff, overhead) per operand dtype (PSVT_DTYPE_*), kind (sym = 1 for
+ * with (eff, overhead) per operand dtype (PSVT_DTYPE_*; for split bf16 the
+ * CU rate is a third of bf16's, so eff is per useful flop), kind (sym = 1 for
  * the lower-triangle products, 0 for full ones) and configuration, measured
  * by the autotuner.
  *   psvt_tune_force_tile(id)   force a configuration on the calling thread

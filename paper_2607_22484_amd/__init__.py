@@ -311,7 +311,9 @@ _DTYPE_OF = {"float32": DTYPE_F32, "bfloat16": DTYPE_BF16, "uint8": DTYPE_FP8, "
 
 def gemm_nt(A, B, D=None, alpha: float = 1.0, beta: float = 0.0, sym: bool = False, out=None, dtype=None):
     """C = alpha A B^T + beta D with the library's MFMA kernel.  A and B hold
-    float32, bfloat16, or FP8 e4m3 bytes (uint8 / float8_e4m3fn tensors)."""
+    float32, bfloat16, or FP8 e4m3 bytes (uint8 / float8_e4m3fn tensors); with
+    dtype=DTYPE_BF16X3 they are split-bf16 pairs of planes as ``convert``
+    writes them (the product is hi.hi + hi.lo + lo.hi)."""
     torch = _torch()
     for X, name in ((A, "A"), (B, "B")):
         if not isinstance(X, torch.Tensor) or X.ndim != 2 or X.device.type != "cuda" or X.stride(1) != 1:
@@ -321,6 +323,10 @@ def gemm_nt(A, B, D=None, alpha: float = 1.0, beta: float = 0.0, sym: bool = Fal
         raise TypeError("unsupported operand dtype %s / %s" % (A.dtype, B.dtype))
     M, K = A.shape
     N, K2 = B.shape
+    if dt == DTYPE_BF16X3:  # split operands: hi plane rows, then lo plane rows (as convert writes them)
+        if M % 2 or N % 2:
+            raise ValueError("split bf16 operands hold two planes of equal height")
+        M, N = M // 2, N // 2
     if K != K2:
         raise ValueError("inner dimensions differ")
     C = out if out is not None else torch.empty((M, N), dtype=torch.float32, device=A.device)

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpsvt.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = ["gemm_f32.hip", "gemm_bf16x3.hip", "gemm_bf16.hip", "gemm_fp8.hip", "kernels.hip", "api.hip",
            "trace.hip", "batch.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -30,7 +31,8 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile every source (in parallel: the per-operand-type tile units
     dominate) and link ``libpsvt.so``."""
     jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
-    objs = [os.path.join(CSRC, src.replace(".hip", ".o")) for src in SOURCES]
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, src.replace(".hip", ".o")) for src in SOURCES]
 
     def one(pair):
         src, obj = pair
@@ -47,8 +49,6 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    for o in objs:
-        os.remove(o)
     return LIB
 
 

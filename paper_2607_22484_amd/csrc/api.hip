@@ -897,7 +897,7 @@ int psvt_tune_load(const char *path) {
         char extra[8];
         const int got = sscanf(line, "%d %d %d %lf %lf %7s", &e.type, &e.id, &e.sym, &e.e, &e.o, extra);
         if (got <= 0) continue;  // blank or comment
-        if (got != 5 || e.type < 0 || e.type > 2 || e.id < 1 || e.id > 4 || (e.sym != 0 && e.sym != 1) ||
+        if (got != 5 || e.type < 0 || e.type > 3 || e.id < 1 || e.id > 4 || (e.sym != 0 && e.sym != 1) ||
             !(e.e > 0.0 && e.e <= 1.0) || !(e.o >= 0.0 && e.o < 1e6) || n >= 64) {
             fclose(f);
             return fail(PSVT_EINVAL, "%s:%d: expected 'dtype id sym efficiency overhead_us'", path, lineno);
@@ -910,7 +910,7 @@ int psvt_tune_load(const char *path) {
 }
 
 int psvt_tune_pick(int dtype, int64_t M, int64_t N, int64_t K, int sym) {
-    if (dtype < 0 || dtype > 2) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
+    if (dtype < 0 || dtype > 3) return fail(PSVT_EINVAL, "bad dtype %d", dtype);
     if (M <= 0 || N <= 0 || K < 0 || M > (1LL << 30) || N > (1LL << 30) || K > (1LL << 30))
         return fail(PSVT_EINVAL, "bad size");
     return tune_pick(dtype, (int)M, (int)N, (int)K, sym ? 1 : 0);

@@ -27,7 +27,8 @@ static const TileCfg kTiles[] = {{0, 0, ""}, {64, 4, "64"}, {128, 2, "128"}, {19
 constexpr int kNumTiles = 4;
 static const char *kTypeTag[4] = {"f32", "bf16", "fp8", "bf16x3"};
 // dense MFMA flop/s of one CU per operand type (257 = 256 CUs + 1)
-static const double kCuRate[3] = {157.3e12 / 256.0, 2516.6e12 / 256.0, 5033.2e12 / 256.0};
+// (split bf16: the useful rate, a third of bf16's, since every product takes three)
+static const double kCuRate[4] = {157.3e12 / 256.0, 2516.6e12 / 256.0, 5033.2e12 / 256.0, 2516.6e12 / 3.0 / 256.0};
 
 // Cost model of one product in configuration c:  time ~= (most tiles on one
 // CU) x (overhead + tile flops / (efficiency x CU MFMA rate)), with the
@@ -37,13 +38,15 @@ static const double kCuRate[3] = {157.3e12 / 256.0, 2516.6e12 / 256.0, 5033.2e12
 struct TileModel {
     float eff, overhead_us;
 };
-static TileModel g_model[3][2][kNumTiles + 1] = {
+static TileModel g_model[4][2][kNumTiles + 1] = {
     {{{0.f, 0.f}, {0.78f, 19.0f}, {0.86f, 51.0f}, {0.73f, 17.0f}, {0.76f, 0.0f}},
      {{0.f, 0.f}, {0.64f, 14.0f}, {0.72f, 20.0f}, {0.72f, 15.0f}, {0.45f, 19.0f}}},
     {{{0.f, 0.f}, {0.30f, 6.0f}, {0.40f, 8.0f}, {0.40f, 10.0f}, {0.45f, 12.0f}},
      {{0.f, 0.f}, {0.30f, 6.0f}, {0.40f, 8.0f}, {0.40f, 10.0f}, {0.45f, 12.0f}}},
     {{{0.f, 0.f}, {0.25f, 6.0f}, {0.35f, 8.0f}, {0.35f, 10.0f}, {0.40f, 12.0f}},
      {{0.f, 0.f}, {0.25f, 6.0f}, {0.35f, 8.0f}, {0.35f, 10.0f}, {0.40f, 12.0f}}},
+    {{{0.f, 0.f}, {0.40f, 8.0f}, {0.45f, 10.0f}, {0.40f, 12.0f}, {0.45f, 14.0f}},
+     {{0.f, 0.f}, {0.40f, 8.0f}, {0.45f, 10.0f}, {0.40f, 12.0f}, {0.45f, 14.0f}}},
 };
 static thread_local int g_force_tile = 0;
 
@@ -53,10 +56,6 @@ static int tile_count(int M, int N, int sym, int bm) {
 }
 
 static double model_time_us(int type, int M, int N, int K, int sym, int c) {
-    if (type == OP_BF16X3) {  // three bf16 passes
-        type = OP_BF16;
-        K *= 3;
-    }
     const double bm = kTiles[c].bm;
     const double per_cu = ceil(tile_count(M, N, sym, kTiles[c].bm) / 256.0);
     const TileModel &tm = g_model[type][sym ? 1 : 0][c];
@@ -107,7 +106,7 @@ hipError_t launch_gemm(const GemmArgs &g_in, int op_type, hipStream_t st) {
 
 void tune_force_tile(int c) { g_force_tile = c; }
 int tune_set_model(int type, int c, int sym, float e, float overhead_us) {
-    if (type < 0 || type > 2 || c < 1 || c > kNumTiles || (sym != 0 && sym != 1) || !(e > 0.0f && e <= 1.0f) ||
+    if (type < 0 || type > 3 || c < 1 || c > kNumTiles || (sym != 0 && sym != 1) || !(e > 0.0f && e <= 1.0f) ||
         !(overhead_us >= 0.0f && overhead_us < 1e6f))
         return -1;
     g_model[type][sym][c] = TileModel{e, overhead_us};

@@ -180,8 +180,12 @@ __device__ __forceinline__ void store_tile(const GemmArgs &g, int bi, int bj, fl
 // MFMA (16 MFMAs per k-tile), bf16 8 (4 MFMAs), fp8 32 (2 MFMAs).
 template <int ET, int BM, int BN>
 struct TileShape {
-    static constexpr int ROWB = 144;  // LDS row stride in bytes
-    static constexpr int SMEM = 2 * (BM + BN) * ROWB;
+    static constexpr int ROWB = 144;  // LDS row stride in bytes (register-staged body)
+    // split bf16 up to 128 x 128: the direct body keeps both planes per stage
+    static constexpr bool FUSED_SPLIT = ET == OP_BF16X3 && BM <= 128 && BN <= 128;
+    static constexpr int STAGED = 2 * (BM + BN) * ROWB;
+    static constexpr int DIRECT = (FUSED_SPLIT ? 4 : 2) * (BM + BN) * 128;
+    static constexpr int SMEM = STAGED > DIRECT ? STAGED : DIRECT;
 };
 
 // Local tile t of a product -> block tile (bi, bj): lower block triangle for
@@ -384,8 +388,15 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
     constexpr int BK = 8 * EPC;
     constexpr int TM = BM / 64, TN = BN / 64;
     constexpr int RA = BM / 32, RB = BN / 32;
-    constexpr int STAGE = (BM + BN) * 128;
     constexpr bool SPLIT = ET == OP_BF16X3;
+    // Split bf16 on tiles up to 128: both planes of a k-tile share one stage
+    // and each fragment pair feeds the three products hi.hi, hi.lo, lo.hi (one
+    // pass over k).  Larger tiles (two planes would not fit twice in LDS) run
+    // three virtual k segments with planes (hi, hi, lo) for A, (hi, lo, hi)
+    // for B.
+    constexpr bool FUSED = TileShape<ET, BM, BN>::FUSED_SPLIT;
+    constexpr int PLANE = (BM + BN) * 128;
+    constexpr int STAGE = FUSED ? 2 * PLANE : PLANE;
     const int i0 = bi * BM, j0 = bj * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -397,47 +408,52 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
     const int lchunk = lslot ^ lrow;  // global chunk this lane fetches (row % 8 == lrow)
     const int nfull = g.K / BK;                // whole k-tiles
     const int nkt = (g.K + BK - 1) / BK;       // k-tiles per segment
-    const int nk = SPLIT ? 3 * nkt : nkt;
-    // Split bf16: three virtual k segments; A reads planes (hi, hi, lo), B (hi, lo, hi).
+    const int nk = (SPLIT && !FUSED) ? 3 * nkt : nkt;
+
+    // R x 8 rows of a tile, one 16-byte chunk per lane and row, straight to LDS
+    auto direct_rows = [&](const __amdgpu_buffer_rsrc_t &rs, int64_t ld, int row0, uint32_t kb, uint8_t *dst,
+                           auto nrep) {
+#pragma unroll
+        for (int p = 0; p < decltype(nrep)::value; ++p) {
+            const int r0 = 8 * (wave + 4 * p);  // first of the 8 rows this wave fills
+            const uint32_t off = (uint32_t)((row0 + r0 + lrow) * ld * ESZ) + kb;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(dst + r0 * 128), 16, off, 0, 0, 0);
+        }
+    };
+    // ragged last k-tile: element-masked register loads (zero beyond K),
+    // written to the same swizzled slots
+    auto masked_rows = [&](const T *P, int64_t ld, int row0, int rows, int k, uint8_t *dst, auto nrep) {
+#pragma unroll
+        for (int p = 0; p < decltype(nrep)::value; ++p) {
+            const int r = 8 * (wave + 4 * p) + lrow;
+            *(u32x4 *)(dst + r * 128 + lslot * 16) = load_chunk_masked<ET>(P, ld, row0 + r, rows, k, g.K);
+        }
+    };
+    const std::integral_constant<int, RA> na{};
+    const std::integral_constant<int, RB> nb{};
     auto issue = [&](int kv, int stage) {
         int seg = 0, kt = kv;
-        if constexpr (SPLIT) {
+        if constexpr (SPLIT && !FUSED) {
             seg = kv / nkt;
             kt = kv - seg * nkt;
         }
         uint8_t *base = smem + stage * STAGE;
         if (kt < nfull) {
-            const __amdgpu_buffer_rsrc_t ra = SPLIT && seg == 2 ? ra_lo : ra_hi;
-            const __amdgpu_buffer_rsrc_t rb = SPLIT && seg == 1 ? rb_lo : rb_hi;
             const uint32_t kb = (uint32_t)kt * BK * ESZ + lchunk * 16;
-#pragma unroll
-            for (int p = 0; p < RA; ++p) {
-                const int r0 = 8 * (wave + 4 * p);  // first of the 8 rows this wave fills
-                const uint32_t off = (uint32_t)((i0 + r0 + lrow) * (int64_t)g.lda * ESZ) + kb;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void *)(base + r0 * 128), 16, off, 0, 0, 0);
-            }
-#pragma unroll
-            for (int p = 0; p < RB; ++p) {
-                const int r0 = 8 * (wave + 4 * p);
-                const uint32_t off = (uint32_t)((j0 + r0 + lrow) * (int64_t)g.ldb * ESZ) + kb;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void *)(base + BM * 128 + r0 * 128), 16, off, 0, 0,
-                                                         0);
+            direct_rows(SPLIT && seg == 2 ? ra_lo : ra_hi, g.lda, i0, kb, base, na);
+            direct_rows(SPLIT && seg == 1 ? rb_lo : rb_hi, g.ldb, j0, kb, base + BM * 128, nb);
+            if constexpr (FUSED) {
+                direct_rows(ra_lo, g.lda, i0, kb, base + PLANE, na);
+                direct_rows(rb_lo, g.ldb, j0, kb, base + PLANE + BM * 128, nb);
             }
         } else {
-            // ragged last k-tile of a segment: element-masked register loads
-            // (zero beyond K), written to the same swizzled slots
-            const T *Ap = (const T *)g.A + (SPLIT && seg == 2 ? g.a_plane : 0);
-            const T *Bp = (const T *)g.B + (SPLIT && seg == 1 ? g.b_plane : 0);
+            const T *A = (const T *)g.A, *B = (const T *)g.B;
             const int k = kt * BK + lchunk * EPC;
-#pragma unroll
-            for (int p = 0; p < RA; ++p) {
-                const int r = 8 * (wave + 4 * p) + lrow;
-                *(u32x4 *)(base + r * 128 + lslot * 16) = load_chunk_masked<ET>(Ap, g.lda, i0 + r, g.M, k, g.K);
-            }
-#pragma unroll
-            for (int p = 0; p < RB; ++p) {
-                const int r = 8 * (wave + 4 * p) + lrow;
-                *(u32x4 *)(base + (BM + r) * 128 + lslot * 16) = load_chunk_masked<ET>(Bp, g.ldb, j0 + r, g.N, k, g.K);
+            masked_rows(A + (SPLIT && seg == 2 ? g.a_plane : 0), g.lda, i0, g.M, k, base, na);
+            masked_rows(B + (SPLIT && seg == 1 ? g.b_plane : 0), g.ldb, j0, g.N, k, base + BM * 128, nb);
+            if constexpr (FUSED) {
+                masked_rows(A + g.a_plane, g.lda, i0, g.M, k, base + PLANE, na);
+                masked_rows(B + g.b_plane, g.ldb, j0, g.N, k, base + PLANE + BM * 128, nb);
             }
         }
     };
@@ -466,11 +482,33 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
                 bf[b][0] = *(const u32x4 *)&Bs[(b * 32 + frow) * 128 + c0];
                 bf[b][1] = *(const u32x4 *)&Bs[(b * 32 + frow) * 128 + c1];
             }
+            if constexpr (FUSED) {
+                u32x4 al[TM][2], bl[TN][2];
 #pragma unroll
-            for (int a = 0; a < TM; ++a)
+                for (int a = 0; a < TM; ++a) {
+                    al[a][0] = *(const u32x4 *)&As[PLANE + (a * 32 + frow) * 128 + c0];
+                    al[a][1] = *(const u32x4 *)&As[PLANE + (a * 32 + frow) * 128 + c1];
+                }
 #pragma unroll
-                for (int b = 0; b < TN; ++b)
-                    acc[a][b] = mfma_32b<ET>(af[a][0], af[a][1], bf[b][0], bf[b][1], acc[a][b]);
+                for (int b = 0; b < TN; ++b) {
+                    bl[b][0] = *(const u32x4 *)&Bs[PLANE + (b * 32 + frow) * 128 + c0];
+                    bl[b][1] = *(const u32x4 *)&Bs[PLANE + (b * 32 + frow) * 128 + c1];
+                }
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b) {
+                        acc[a][b] = mfma_32b<ET>(af[a][0], af[a][1], bf[b][0], bf[b][1], acc[a][b]);
+                        acc[a][b] = mfma_32b<ET>(af[a][0], af[a][1], bl[b][0], bl[b][1], acc[a][b]);
+                        acc[a][b] = mfma_32b<ET>(al[a][0], al[a][1], bf[b][0], bf[b][1], acc[a][b]);
+                    }
+            } else {
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b = 0; b < TN; ++b)
+                        acc[a][b] = mfma_32b<ET>(af[a][0], af[a][1], bf[b][0], bf[b][1], acc[a][b]);
+            }
         }
     };
     issue(0, 0);
@@ -543,13 +581,19 @@ hipError_t gemm_launch_bm(const GemmArgs &g, int nblocks, hipStream_t st) {
     return hipGetLastError();
 }
 
+// blocks per CU a configuration targets (LDS-limited: 160 KB per CU)
+template <int ET, int BM>
+constexpr int tile_occupancy() {
+    return (160 * 1024) / TileShape<ET, BM, BM>::SMEM < 4 ? (160 * 1024) / TileShape<ET, BM, BM>::SMEM : 4;
+}
+
 template <int ET>
 hipError_t gemm_launch(const GemmArgs &g, int tile, int nblocks, hipStream_t st) {
     switch (tile) {
-        case 1: return gemm_launch_bm<ET, 64, 4>(g, nblocks, st);
+        case 1: return gemm_launch_bm<ET, 64, tile_occupancy<ET, 64>()>(g, nblocks, st);
         case 3: return gemm_launch_bm<ET, 192, 1>(g, nblocks, st);
         case 4: return gemm_launch_bm<ET, 256, 1>(g, nblocks, st);
-        default: return gemm_launch_bm<ET, 128, 2>(g, nblocks, st);
+        default: return gemm_launch_bm<ET, 128, tile_occupancy<ET, 128>()>(g, nblocks, st);
     }
 }
 
@@ -571,10 +615,10 @@ template <int ET>
 hipError_t gemm_launch_grouped(const GemmArgs *args, const int *prefix, int n, int total, int tile, int sym,
                                int two_a, hipStream_t st) {
     switch (tile) {
-        case 1: return gemm_grouped_bm<ET, 64, 4>(args, prefix, n, total, sym, two_a, st);
+        case 1: return gemm_grouped_bm<ET, 64, tile_occupancy<ET, 64>()>(args, prefix, n, total, sym, two_a, st);
         case 3: return gemm_grouped_bm<ET, 192, 1>(args, prefix, n, total, sym, two_a, st);
         case 4: return gemm_grouped_bm<ET, 256, 1>(args, prefix, n, total, sym, two_a, st);
-        default: return gemm_grouped_bm<ET, 128, 2>(args, prefix, n, total, sym, two_a, st);
+        default: return gemm_grouped_bm<ET, 128, tile_occupancy<ET, 128>()>(args, prefix, n, total, sym, two_a, st);
     }
 }
 

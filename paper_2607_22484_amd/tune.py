@@ -24,11 +24,13 @@ import math
 import os
 import sys
 
-CU_RATES = {0: 157.3e12 / 256, 1: 2516.6e12 / 256, 2: 5033.2e12 / 256}  # MFMA flop/s of one CU per dtype
+# MFMA flop/s of one CU per dtype (split bf16: the useful rate, a third of bf16's)
+CU_RATES = {0: 157.3e12 / 256, 1: 2516.6e12 / 256, 2: 5033.2e12 / 256, 3: 2516.6e12 / 3 / 256}
 CU_RATE = CU_RATES[0]
 TILES = {1: 64, 2: 128, 3: 192, 4: 256}
-DTYPES = (0, 1, 2)
+DTYPES = (0, 1, 2, 3)
 SHAPES = [  # (M, N, K, sym)
+    (256, 256, 768, True), (768, 256, 256, False), (640, 640, 1280, True), (1280, 640, 640, False),
     (512, 512, 512, True), (1024, 1024, 1024, True), (2048, 2048, 2048, True), (3072, 3072, 3072, True),
     (4096, 4096, 4096, True), (4096, 4096, 8192, True), (1024, 1024, 1024, False), (2048, 2048, 2048, False),
     (4096, 4096, 4096, False), (8192, 4096, 4096, False),
