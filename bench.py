@@ -268,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
+    ap.add_argument("--forms", default="precision,batched,serving",
+                    help="comma-separated subset of the precision / batched / serving legs to run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
@@ -379,13 +381,17 @@ def main():
         del A, Y, ws
         torch.cuda.empty_cache()
         forms = {}
-        print("[bench] precision form ...", file=sys.stderr, flush=True)
-        forms["precision"] = precision_leg(psvt, torch, dev, not args.no_cpu)
-        print("[bench] batched form ...", file=sys.stderr, flush=True)
-        forms["batched"] = batched_leg(psvt, torch, dev, not args.no_cpu)
-        torch.cuda.empty_cache()
-        print("[bench] serving form ...", file=sys.stderr, flush=True)
-        forms["serving"] = serving_leg(psvt, torch, dev)
+        want = set(args.forms.split(","))
+        if "precision" in want:
+            print("[bench] precision form ...", file=sys.stderr, flush=True)
+            forms["precision"] = precision_leg(psvt, torch, dev, not args.no_cpu)
+        if "batched" in want:
+            print("[bench] batched form ...", file=sys.stderr, flush=True)
+            forms["batched"] = batched_leg(psvt, torch, dev, not args.no_cpu)
+            torch.cuda.empty_cache()
+        if "serving" in want:
+            print("[bench] serving form ...", file=sys.stderr, flush=True)
+            forms["serving"] = serving_leg(psvt, torch, dev)
         out["forms"] = forms
     print(json.dumps(out), flush=True)
 

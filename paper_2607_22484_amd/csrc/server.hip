@@ -9,7 +9,8 @@
 // grouped by kind (products also by operand type and tile configuration)
 // into grouped launches, so requests at different points of their iteration
 // share launches and a request admitted during the run joins at the next
-// tick.  Each product tile is computed exactly as in a single call, so a
+// tick.  The groups of a round touch disjoint requests and run concurrently
+// on the server's stream and three side streams.  Each product tile is computed exactly as in a single call, so a
 // result does not depend on what it was batched with.  At most `depth` ticks
 // are in flight on the stream; a request completes when the event of the
 // tick that launched its last stage has passed, and its workspace returns to
@@ -129,6 +130,12 @@ struct psvt_server {
     std::vector<hipEvent_t> seg_event;
     std::vector<int64_t> seg_tick;
     hipStream_t stream = nullptr;
+    // the groups of one round touch disjoint requests: they run concurrently
+    // on `stream` and kSide side streams (forked after the descriptor copy,
+    // joined back into `stream` before the next round)
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t ev_copy = nullptr, ev_side[kSide] = {};
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -167,6 +174,15 @@ int launch_round(psvt_server *s, std::vector<Request *> &reqs, int seg, size_t &
     }
     char *hseg = s->ring_host + (size_t)seg * psvt_server::kSegBytes;
     char *dseg = s->ring_dev + (size_t)seg * psvt_server::kSegBytes;
+    struct Group {
+        GroupKey k;
+        size_t off;  // descriptors at off, prefix after them
+        int n, total;
+        double flops, bytes;
+    };
+    std::vector<Group> gl;
+    const size_t round_start = seg_used;
+    // host: every group's descriptors into this round's part of the segment
     for (auto &kv : groups) {
         const GroupKey &k = kv.first;
         auto &rs = kv.second;
@@ -179,44 +195,55 @@ int launch_round(psvt_server *s, std::vector<Request *> &reqs, int seg, size_t &
         const size_t need = align256(esz * rs.size()) + align256(sizeof(int) * rs.size());
         if (seg_used + need > psvt_server::kSegBytes) return set_error(PSVT_EINVAL, "server descriptor segment full");
         char *hops = hseg + seg_used, *hpre = hops + align256(esz * rs.size());
-        const char *dops = dseg + seg_used, *dpre = dops + align256(esz * rs.size());
-        int total = 0;
-        double flops = 0.0, bytes = 0.0;
+        Group G{k, seg_used, (int)rs.size(), 0, 0.0, 0.0};
         for (size_t i = 0; i < rs.size(); ++i) {
             const Stage &st = rs[i]->plan[rs[i]->cursor];
-            ((int *)hpre)[i] = total;
+            ((int *)hpre)[i] = G.total;
             if (k.kind == ST_GEMM) {
                 ((GemmArgs *)hops)[i] = st.g;
-                total += gemm_tile_count(st.g, k.tile);
-                flops += st.g.sym ? (double)st.g.M * (st.g.M + 1) * st.g.K : 2.0 * st.g.M * st.g.N * st.g.K;
+                G.total += gemm_tile_count(st.g, k.tile);
+                G.flops += st.g.sym ? (double)st.g.M * (st.g.M + 1) * st.g.K : 2.0 * st.g.M * st.g.N * st.g.K;
             } else if (k.kind == ST_NORM) {
                 ((NormOp *)hops)[i] = st.n;
-                total += st.n.nparts;
-                bytes += 4.0 * st.n.rows * st.n.cols;
+                G.total += st.n.nparts;
+                G.bytes += 4.0 * st.n.rows * st.n.cols;
             } else {
                 ((TileOp *)hops)[i] = st.t;
-                total += tile_op_tiles(st.t);
-                bytes += tile_op_bytes(st.t);
+                G.total += tile_op_tiles(st.t);
+                G.bytes += tile_op_bytes(st.t);
             }
         }
         seg_used += need;
-        s->launches += 1;
-        if (s->fake) continue;
-        hipError_t e = hipMemcpyAsync((void *)dops, hops, need, hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess) {
-            const int n = (int)rs.size();
-            if (k.kind == ST_GEMM)
-                e = launch_gemm_grouped((const GemmArgs *)dops, (const int *)dpre, n, total, k.dtype, k.tile, k.sym,
-                                        k.two_a, flops, s->stream);
-            else if (k.kind == ST_NORM)
-                e = launch_norm_grouped((const NormOp *)dops, (const int *)dpre, n, total, bytes, s->stream);
-            else
-                e = launch_tile_op_grouped((const TileOp *)dops, (const int *)dpre, n, total, k.tkind, bytes,
-                                           s->stream);
-        }
-        if (e != hipSuccess) return set_error(PSVT_EHIP, hipGetErrorString(e));
+        gl.push_back(G);
     }
+    s->launches += (int64_t)gl.size();
     for (Request *r : reqs) r->cursor++;
+    if (s->fake || gl.empty()) return PSVT_OK;
+    // device: one descriptor copy, then the groups spread over the streams
+    hipError_t e = hipMemcpyAsync(dseg + round_start, hseg + round_start, seg_used - round_start,
+                                  hipMemcpyHostToDevice, s->stream);
+    const int nside = std::min<int>(psvt_server::kSide, (int)gl.size() - 1);
+    if (e == hipSuccess && nside > 0) e = hipEventRecord(s->ev_copy, s->stream);
+    for (int j = 0; j < nside && e == hipSuccess; ++j) e = hipStreamWaitEvent(s->side[j], s->ev_copy, 0);
+    for (size_t gi = 0; gi < gl.size() && e == hipSuccess; ++gi) {
+        const Group &G = gl[gi];
+        const GroupKey &k = G.k;
+        hipStream_t st = gi == 0 ? s->stream : s->side[(gi - 1) % psvt_server::kSide];
+        const size_t esz = k.kind == ST_GEMM ? sizeof(GemmArgs) : (k.kind == ST_NORM ? sizeof(NormOp) : sizeof(TileOp));
+        const char *dops = dseg + G.off, *dpre = dops + align256(esz * G.n);
+        if (k.kind == ST_GEMM)
+            e = launch_gemm_grouped((const GemmArgs *)dops, (const int *)dpre, G.n, G.total, k.dtype, k.tile, k.sym,
+                                    k.two_a, G.flops, st);
+        else if (k.kind == ST_NORM)
+            e = launch_norm_grouped((const NormOp *)dops, (const int *)dpre, G.n, G.total, G.bytes, st);
+        else
+            e = launch_tile_op_grouped((const TileOp *)dops, (const int *)dpre, G.n, G.total, k.tkind, G.bytes, st);
+    }
+    for (int j = 0; j < nside && e == hipSuccess; ++j) {
+        e = hipEventRecord(s->ev_side[j], s->side[j]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->ev_side[j], 0);
+    }
+    if (e != hipSuccess) return set_error(PSVT_EHIP, hipGetErrorString(e));
     return PSVT_OK;
 }
 
@@ -372,6 +399,11 @@ int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config
         if (e == hipSuccess) e = hipHostMalloc((void **)&s->ring_host, psvt_server::kSegBytes * s->nseg, 0);
         if (e == hipSuccess) e = hipMalloc((void **)&s->ring_dev, psvt_server::kSegBytes * s->nseg);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        for (int j = 0; j < psvt_server::kSide && e == hipSuccess; ++j) {
+            e = hipStreamCreateWithFlags(&s->side[j], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_side[j], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming);
         for (int i = 0; i < s->nseg && e == hipSuccess; ++i) {
             hipEvent_t ev;
             e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -492,6 +524,12 @@ int psvt_server_destroy(psvt_server *s) {
     if (s->worker.joinable()) s->worker.join();
     if (!s->fake) {
         if (s->stream) (void)hipStreamSynchronize(s->stream);
+        for (int j = 0; j < psvt_server::kSide; ++j) {
+            if (s->side[j]) (void)hipStreamSynchronize(s->side[j]);
+            if (s->side[j]) (void)hipStreamDestroy(s->side[j]);
+            if (s->ev_side[j]) (void)hipEventDestroy(s->ev_side[j]);
+        }
+        if (s->ev_copy) (void)hipEventDestroy(s->ev_copy);
         for (hipEvent_t e : s->seg_event) (void)hipEventDestroy(e);
         if (s->stream) (void)hipStreamDestroy(s->stream);
         if (s->ring_dev) (void)hipFree(s->ring_dev);
