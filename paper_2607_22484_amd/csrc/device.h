@@ -86,4 +86,38 @@ __device__ __forceinline__ void store_lp(void *base, int type, int64_t idx, floa
     }
 }
 
+// Four consecutive elements idx .. idx+3 of a low-precision copy in one store
+// per plane (8 bytes of bf16, 4 of fp8) when the address allows it; the same
+// bytes as four store_lp calls.
+__device__ __forceinline__ void store_lp4(void *base, int type, int64_t idx, const float v[4], float scale,
+                                          int64_t plane = 0) {
+    const int esz = type == OP_FP8 ? 1 : 2;
+    const uintptr_t addr = (uintptr_t)base + (uintptr_t)(idx * esz);
+    const uintptr_t addr_lo = (uintptr_t)base + (uintptr_t)((idx + plane) * esz);
+    if ((addr & (4 * esz - 1)) != 0 || (type == OP_BF16X3 && (addr_lo & 7) != 0)) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) store_lp(base, type, idx + e, v[e] * scale, plane);
+        return;
+    }
+    if (type == OP_FP8) {
+        float c[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[e] = fminf(fmaxf(v[e] * scale, -448.0f), 448.0f);
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], w, true);
+        *(uint32_t *)addr = (uint32_t)w;
+        return;
+    }
+    uint16_t hi[4], lo[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float x = v[e] * scale;
+        hi[e] = to_bf16(x);
+        lo[e] = to_bf16(x - __uint_as_float((uint32_t)hi[e] << 16));
+    }
+    *(uint2 *)addr = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
+    if (type == OP_BF16X3)
+        *(uint2 *)addr_lo = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+}
+
 }  // namespace psvt

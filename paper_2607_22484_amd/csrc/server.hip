@@ -9,12 +9,13 @@
 // grouped by kind (products also by operand type and tile configuration)
 // into grouped launches, so requests at different points of their iteration
 // share launches and a request admitted during the run joins at the next
-// tick.  The groups of a round touch disjoint requests and run concurrently
-// on the server's stream and three side streams.  Each product tile is computed exactly as in a single call, so a
-// result does not depend on what it was batched with.  At most `depth` ticks
-// are in flight on the stream; a request completes when the event of the
-// tick that launched its last stage has passed, and its workspace returns to
-// the pool.
+// tick.  Requests are split by size into lanes; each lane runs its own ticks
+// on its own stream, so lanes overlap on the device and small requests do
+// not advance at the pace of the largest stages.  Each product tile is computed exactly as in a single call, so a
+// result does not depend on what it was batched with.  At most `depth` + 1
+// ticks of a lane are in flight on its stream; a request completes when the
+// event of the tick that launched its last stage has passed, and its
+// workspace returns to the pool.
 //
 // With PSVT_SERVER_FAKE the same scheduler runs without a device: stages
 // complete immediately (for testing admission and scheduling on a CPU).
@@ -107,9 +108,20 @@ struct Request {
     std::vector<Stage> plan;
     size_t cursor = 0;
     int state = RQ_QUEUED;
-    int64_t finish_tick = -1;
+    int64_t finish_tick = -1;  // lane tick that launched the last stage
+    int lane = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
 };
+
+// Lane of a request: by s^2 l (s, l the short and long side), the scale of
+// its flops, in factors of 8 from 512^3.
+int lane_of(const psvt_batch_item &it, int nlanes) {
+    const double s = (double)std::min(it.m, it.n), l = (double)std::max(it.m, it.n);
+    const double w = s * s * l;
+    int lane = 0;
+    for (double t = 512.0 * 512.0 * 512.0; lane < nlanes - 1 && w > t; t *= 8.0) ++lane;
+    return lane;
+}
 
 }  // namespace
 
@@ -123,19 +135,23 @@ struct psvt_server {
     Pool *pool = nullptr;
     int device = 0;
 
-    // descriptor ring: one segment per in-flight tick
+    // Lanes: requests are assigned by size (s^2 l, the flop scale) to one of
+    // kLanes lanes; a lane runs its own ticks on its own stream, so small
+    // requests do not advance at the pace of the largest stages, and the
+    // lanes' launches overlap on the device.  Each lane has a descriptor ring
+    // of one 1 MiB segment per in-flight tick.
     static constexpr size_t kSegBytes = 1 << 20;
+    static constexpr int kLanes = 4;
+    struct Lane {
+        hipStream_t stream = nullptr;
+        std::vector<hipEvent_t> seg_event;
+        std::vector<int64_t> seg_tick;
+        int64_t tick = 0;
+        char *ring_host = nullptr, *ring_dev = nullptr;
+    };
+    Lane lanes[kLanes];
     int nseg = 0;
-    char *ring_host = nullptr, *ring_dev = nullptr;
-    std::vector<hipEvent_t> seg_event;
-    std::vector<int64_t> seg_tick;
-    hipStream_t stream = nullptr;
-    // the groups of one round touch disjoint requests: they run concurrently
-    // on `stream` and kSide side streams (forked after the descriptor copy,
-    // joined back into `stream` before the next round)
-    static constexpr int kSide = 3;
-    hipStream_t side[kSide] = {};
-    hipEvent_t ev_copy = nullptr, ev_side[kSide] = {};
+    char *ring_host = nullptr, *ring_dev = nullptr;  // all lanes' segments
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -163,7 +179,7 @@ struct GroupKey {
     }
 };
 
-int launch_round(psvt_server *s, std::vector<Request *> &reqs, int seg, size_t &seg_used) {
+int launch_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *> &reqs, int seg, size_t &seg_used) {
     std::map<GroupKey, std::vector<Request *>> groups;
     for (Request *r : reqs) {
         const Stage &st = r->plan[r->cursor];
@@ -172,8 +188,8 @@ int launch_round(psvt_server *s, std::vector<Request *> &reqs, int seg, size_t &
                    st.kind == ST_TILE ? st.t.kind : 0};
         groups[k].push_back(r);
     }
-    char *hseg = s->ring_host + (size_t)seg * psvt_server::kSegBytes;
-    char *dseg = s->ring_dev + (size_t)seg * psvt_server::kSegBytes;
+    char *hseg = lane.ring_host + (size_t)seg * psvt_server::kSegBytes;
+    char *dseg = lane.ring_dev + (size_t)seg * psvt_server::kSegBytes;
     struct Group {
         GroupKey k;
         size_t off;  // descriptors at off, prefix after them
@@ -219,29 +235,22 @@ int launch_round(psvt_server *s, std::vector<Request *> &reqs, int seg, size_t &
     s->launches += (int64_t)gl.size();
     for (Request *r : reqs) r->cursor++;
     if (s->fake || gl.empty()) return PSVT_OK;
-    // device: one descriptor copy, then the groups spread over the streams
+    // device: one descriptor copy, then the groups, on the lane's stream
     hipError_t e = hipMemcpyAsync(dseg + round_start, hseg + round_start, seg_used - round_start,
-                                  hipMemcpyHostToDevice, s->stream);
-    const int nside = std::min<int>(psvt_server::kSide, (int)gl.size() - 1);
-    if (e == hipSuccess && nside > 0) e = hipEventRecord(s->ev_copy, s->stream);
-    for (int j = 0; j < nside && e == hipSuccess; ++j) e = hipStreamWaitEvent(s->side[j], s->ev_copy, 0);
+                                  hipMemcpyHostToDevice, lane.stream);
     for (size_t gi = 0; gi < gl.size() && e == hipSuccess; ++gi) {
         const Group &G = gl[gi];
         const GroupKey &k = G.k;
-        hipStream_t st = gi == 0 ? s->stream : s->side[(gi - 1) % psvt_server::kSide];
         const size_t esz = k.kind == ST_GEMM ? sizeof(GemmArgs) : (k.kind == ST_NORM ? sizeof(NormOp) : sizeof(TileOp));
         const char *dops = dseg + G.off, *dpre = dops + align256(esz * G.n);
         if (k.kind == ST_GEMM)
             e = launch_gemm_grouped((const GemmArgs *)dops, (const int *)dpre, G.n, G.total, k.dtype, k.tile, k.sym,
-                                    k.two_a, G.flops, st);
+                                    k.two_a, G.flops, lane.stream);
         else if (k.kind == ST_NORM)
-            e = launch_norm_grouped((const NormOp *)dops, (const int *)dpre, G.n, G.total, G.bytes, st);
+            e = launch_norm_grouped((const NormOp *)dops, (const int *)dpre, G.n, G.total, G.bytes, lane.stream);
         else
-            e = launch_tile_op_grouped((const TileOp *)dops, (const int *)dpre, G.n, G.total, k.tkind, G.bytes, st);
-    }
-    for (int j = 0; j < nside && e == hipSuccess; ++j) {
-        e = hipEventRecord(s->ev_side[j], s->side[j]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, s->ev_side[j], 0);
+            e = launch_tile_op_grouped((const TileOp *)dops, (const int *)dpre, G.n, G.total, k.tkind, G.bytes,
+                                       lane.stream);
     }
     if (e != hipSuccess) return set_error(PSVT_EHIP, hipGetErrorString(e));
     return PSVT_OK;
@@ -265,7 +274,6 @@ void finish(psvt_server *s, Request *r, int state) {
 
 void worker_main(psvt_server *s) {
     if (!s->fake) (void)hipSetDevice(s->device);
-    int64_t tick = 0;
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         // admission: arrival order, one slot and pool room per request
@@ -285,6 +293,7 @@ void worker_main(psvt_server *s) {
                 continue;
             }
             r->state = RQ_RUNNING;
+            r->lane = lane_of(r->item, psvt_server::kLanes);
             s->active.push_back(r);
         }
         // completions
@@ -296,8 +305,9 @@ void worker_main(psvt_server *s) {
                 if (s->fake) {
                     done = true;
                 } else {
+                    const psvt_server::Lane &ln = s->lanes[r->lane];
                     const int seg = (int)(r->finish_tick % s->nseg);
-                    done = s->seg_tick[seg] != r->finish_tick || hipEventQuery(s->seg_event[seg]) == hipSuccess;
+                    done = ln.seg_tick[seg] != r->finish_tick || hipEventQuery(ln.seg_event[seg]) == hipSuccess;
                 }
             }
             if (done) {
@@ -313,47 +323,52 @@ void worker_main(psvt_server *s) {
             s->cv_done.notify_all();
             continue;  // admit into the freed room first
         }
-        std::vector<Request *> runnable;
-        for (Request *r : s->active)
-            if (r->cursor < r->plan.size()) runnable.push_back(r);
-        if (runnable.empty()) {
+        // one tick per lane that has runnable requests and a free segment
+        bool any_runnable = false, launched = false;
+        for (int li = 0; li < psvt_server::kLanes; ++li) {
+            psvt_server::Lane &ln = s->lanes[li];
+            std::vector<Request *> runnable;
+            for (Request *r : s->active)
+                if (r->lane == li && r->cursor < r->plan.size()) runnable.push_back(r);
+            if (runnable.empty()) continue;
+            any_runnable = true;
+            // reuse the lane's oldest segment only once its tick has finished
+            const int seg = (int)(ln.tick % s->nseg);
+            if (!s->fake && ln.seg_tick[seg] >= 0 && hipEventQuery(ln.seg_event[seg]) != hipSuccess) continue;
+            size_t seg_used = 0;
+            int rc = PSVT_OK;
+            for (int round = 0; round < s->rounds && rc == PSVT_OK; ++round) {
+                std::vector<Request *> rr;
+                for (Request *r : runnable)
+                    if (r->cursor < r->plan.size()) rr.push_back(r);
+                if (rr.empty()) break;
+                rc = launch_round(s, ln, rr, seg, seg_used);
+            }
+            if (!s->fake) {
+                (void)hipEventRecord(ln.seg_event[seg], ln.stream);
+                ln.seg_tick[seg] = ln.tick;
+            }
+            for (Request *r : runnable)
+                if (r->cursor >= r->plan.size() && r->finish_tick < 0) r->finish_tick = ln.tick;
+            s->ticks++;
+            ++ln.tick;
+            launched = true;
+            if (rc != PSVT_OK) {
+                s->error = rc;
+                for (Request *r : runnable) {
+                    finish(s, r, RQ_FAILED);
+                    s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+                }
+                s->cv_done.notify_all();
+            }
+        }
+        if (!any_runnable) {
             if (s->stop && s->queue.empty() && s->active.empty()) break;
             // wait for arrivals or for in-flight ticks to finish
             s->cv_work.wait_for(lk, std::chrono::microseconds(s->active.empty() ? 2000 : 50));
-            continue;
-        }
-        // one tick: reuse the oldest segment once its tick has finished
-        const int seg = (int)(tick % s->nseg);
-        if (!s->fake && s->seg_tick[seg] >= 0) {
-            hipEvent_t ev = s->seg_event[seg];
-            lk.unlock();
-            (void)hipEventSynchronize(ev);
-            lk.lock();
-        }
-        size_t seg_used = 0;
-        int rc = PSVT_OK;
-        for (int round = 0; round < s->rounds && rc == PSVT_OK; ++round) {
-            std::vector<Request *> rr;
-            for (Request *r : runnable)
-                if (r->cursor < r->plan.size()) rr.push_back(r);
-            if (rr.empty()) break;
-            rc = launch_round(s, rr, seg, seg_used);
-        }
-        if (!s->fake) {
-            (void)hipEventRecord(s->seg_event[seg], s->stream);
-            s->seg_tick[seg] = tick;
-        }
-        for (Request *r : runnable)
-            if (r->cursor >= r->plan.size() && r->finish_tick < 0) r->finish_tick = tick;
-        s->ticks++;
-        ++tick;
-        if (rc != PSVT_OK) {
-            s->error = rc;
-            for (Request *r : runnable) {
-                finish(s, r, RQ_FAILED);
-                s->active.erase(std::find(s->active.begin(), s->active.end(), r));
-            }
-            s->cv_done.notify_all();
+        } else if (!launched) {
+            // every lane with work still has all its segments in flight
+            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
         }
     }
 }
@@ -389,33 +404,37 @@ int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config
             s->cfg.coeffs = s->coeffs.data();
         }
     }
-    // descriptor ring: depth + 1 segments of 1 MiB
+    // descriptor rings: depth + 1 segments of 1 MiB per lane
     s->nseg = s->depth + 1;
-    s->seg_tick.assign(s->nseg, -1);
+    for (auto &ln : s->lanes) ln.seg_tick.assign(s->nseg, -1);
     s->pool = new Pool(budget_bytes);
+    const size_t ring_bytes = psvt_server::kSegBytes * s->nseg * psvt_server::kLanes;
     if (!s->fake) {
         hipError_t e = hipGetDevice(&s->device);
         if (e == hipSuccess) e = hipMalloc((void **)&s->pool_dev, budget_bytes);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&s->ring_host, psvt_server::kSegBytes * s->nseg, 0);
-        if (e == hipSuccess) e = hipMalloc((void **)&s->ring_dev, psvt_server::kSegBytes * s->nseg);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-        for (int j = 0; j < psvt_server::kSide && e == hipSuccess; ++j) {
-            e = hipStreamCreateWithFlags(&s->side[j], hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_side[j], hipEventDisableTiming);
-        }
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_copy, hipEventDisableTiming);
-        for (int i = 0; i < s->nseg && e == hipSuccess; ++i) {
-            hipEvent_t ev;
-            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e == hipSuccess) s->seg_event.push_back(ev);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&s->ring_host, ring_bytes, 0);
+        if (e == hipSuccess) e = hipMalloc((void **)&s->ring_dev, ring_bytes);
+        for (int li = 0; li < psvt_server::kLanes && e == hipSuccess; ++li) {
+            psvt_server::Lane &ln = s->lanes[li];
+            e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
+            for (int i = 0; i < s->nseg && e == hipSuccess; ++i) {
+                hipEvent_t ev;
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e == hipSuccess) ln.seg_event.push_back(ev);
+            }
         }
         if (e != hipSuccess) {
             psvt_server_destroy(s);
             return set_error(PSVT_EHIP, hipGetErrorString(e));
         }
     } else {
-        s->ring_host = (char *)malloc(psvt_server::kSegBytes * s->nseg);
+        s->ring_host = (char *)malloc(ring_bytes);
         s->ring_dev = s->ring_host;
+    }
+    for (int li = 0; li < psvt_server::kLanes; ++li) {
+        const size_t off = psvt_server::kSegBytes * s->nseg * li;
+        s->lanes[li].ring_host = s->ring_host ? s->ring_host + off : nullptr;
+        s->lanes[li].ring_dev = s->ring_dev ? s->ring_dev + off : nullptr;
     }
     s->worker = std::thread(worker_main, s);
     *out = s;
@@ -523,15 +542,11 @@ int psvt_server_destroy(psvt_server *s) {
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     if (!s->fake) {
-        if (s->stream) (void)hipStreamSynchronize(s->stream);
-        for (int j = 0; j < psvt_server::kSide; ++j) {
-            if (s->side[j]) (void)hipStreamSynchronize(s->side[j]);
-            if (s->side[j]) (void)hipStreamDestroy(s->side[j]);
-            if (s->ev_side[j]) (void)hipEventDestroy(s->ev_side[j]);
+        for (auto &ln : s->lanes) {
+            if (ln.stream) (void)hipStreamSynchronize(ln.stream);
+            for (hipEvent_t e : ln.seg_event) (void)hipEventDestroy(e);
+            if (ln.stream) (void)hipStreamDestroy(ln.stream);
         }
-        if (s->ev_copy) (void)hipEventDestroy(s->ev_copy);
-        for (hipEvent_t e : s->seg_event) (void)hipEventDestroy(e);
-        if (s->stream) (void)hipStreamDestroy(s->stream);
         if (s->ring_dev) (void)hipFree(s->ring_dev);
         if (s->ring_host) (void)hipHostFree(s->ring_host);
         if (s->pool_dev) (void)hipFree(s->pool_dev);

@@ -135,9 +135,14 @@ __device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j,
     void *ctl = SYM ? g.Clp : g.CTlp;
     const int64_t ldctl = SYM ? g.ldclp : g.ldctlp;
     if (ctl) {
+        const int64_t plane = SYM ? g.lp_plane : g.lp_plane_t;
+        if (t[0] && t[1] && t[2] && t[3]) {
+            store_lp4(ctl, g.lp_type, (int64_t)j * ldctl + ib, v, g.lp_scale, plane);
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (t[e]) store_lp(ctl, g.lp_type, (int64_t)j * ldctl + ib + e, v[e] * g.lp_scale, SYM ? g.lp_plane : g.lp_plane_t);
+            for (int e = 0; e < 4; ++e)
+                if (t[e]) store_lp(ctl, g.lp_type, (int64_t)j * ldctl + ib + e, v[e] * g.lp_scale, plane);
+        }
     }
 }
 

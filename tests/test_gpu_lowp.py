@@ -148,6 +148,29 @@ def test_split_bf16_gemm(gpu_lib, tdev, tile, M, N, K, sym):
     assert np.max(np.abs(got - exact) / ((np.abs(A) @ np.abs(B).T) + 1e-30)) < 2.0 ** -14
 
 
+def test_split_bf16_binding_roundtrip(gpu_lib, tdev):
+    """convert(X, DTYPE_BF16X3) writes the hi plane then the lo plane, and the
+    binding's gemm_nt multiplies such pairs: equal to hi.hi + hi.lo + lo.hi
+    of the planes it wrote (k = 384: whole k-tiles, fused planes)."""
+    torch, dev = tdev
+    _announce("split binding roundtrip")
+    rng = np.random.default_rng(77)
+    A = rng.standard_normal((96, 384)).astype(np.float32)
+    B = rng.standard_normal((72, 384)).astype(np.float32)
+    Ap = gpu_lib.convert(torch.from_numpy(A).to(dev), gpu_lib.DTYPE_BF16X3)
+    Bp = gpu_lib.convert(torch.from_numpy(B).to(dev), gpu_lib.DTYPE_BF16X3)
+    assert tuple(Ap.shape) == (192, 384)
+    ah, al = [host(x).float().numpy().astype(np.float64) for x in (Ap[:96], Ap[96:])]
+    bh, bl = [host(x).float().numpy().astype(np.float64) for x in (Bp[:72], Bp[72:])]
+    assert np.array_equal(ah, bf16_round(A).astype(np.float64))
+    assert np.array_equal(al, bf16_round(A - bf16_round(A)).astype(np.float64))
+    out = torch.zeros((96, 72), device=dev)
+    C = host(gpu_lib.gemm_nt(Ap, Bp, out=out, dtype=gpu_lib.DTYPE_BF16X3)).numpy().astype(np.float64)
+    ref = ah @ bh.T + ah @ bl.T + al @ bh.T
+    bound = (np.abs(ah) @ np.abs(bh).T) * (3 * 384 + 2) * 2.0 ** -24
+    assert np.all(np.abs(C - ref) <= bound + 1e-30)
+
+
 # ------------------------------------------------------ precision schedules
 
 def _noisy(m, n, r=40, idx=0):
