@@ -29,6 +29,20 @@ def test_fake_server_completes_everything():
     srv.close()
 
 
+def test_mixed_sizes_over_all_lanes():
+    """Requests from 64^2 to 4096 x 2048 fall into all four size lanes (s^2 l
+    in factors of 8 from 512^3), each lane running its own ticks: every
+    request completes."""
+    srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, fake=True)
+    shapes = [(4096, 2048), (2048, 2048), (1024, 1024), (512, 512), (64, 64)] * 6
+    tickets = [submit(srv, m, n) for m, n in shapes]
+    srv.drain(timeout=60)
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in tickets)
+    st = srv.stats()
+    assert st["completed"] == len(shapes) and st["failed"] == 0
+    srv.close()
+
+
 def test_budget_limits_concurrency():
     """With room for exactly two requests at a time, peak pool use never
     exceeds the budget and every request still completes."""
