@@ -96,9 +96,11 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline_leg(problems, results, n_sample):
-    """FP64 Jacobi oracle timed on a bounded sample, plus the accuracy of the
-    GPU results against the oracle (constructed factors: Eq. (1) exactly)."""
+def cpu_baseline_leg(problems, results, n_sample, checks):
+    """The FP64 Jacobi oracle on the host cores: timed on a bounded sample of
+    the main workload, and used for every accuracy figure of the run (the
+    GPU legs hand over host copies of their outputs in ``checks``; nothing
+    else in this file calls the oracle)."""
     import oracle
     from paper_2607_22484_amd import inputs
 
@@ -109,6 +111,8 @@ def cpu_baseline_leg(problems, results, n_sample):
         err = np.linalg.norm(Y - ref)
         delta = float(np.linalg.norm(pb.A.astype(np.float64) - pb.A64))  # prox is 1-Lipschitz
         errs[pb.name] = {"rel_err": float(err / nref), "rel_err_bound_fp32_input": float((err + delta) / (nref - delta))}
+    for check in checks:
+        check(oracle)
     sample = inputs.square_case(0.5, n=n_sample)
     t0 = time.perf_counter()
     oracle.svt(sample.A, sample.tau)
@@ -139,7 +143,7 @@ def time_calls(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def precision_leg(psvt, torch, dev, check_oracle):
+def precision_leg(psvt, torch, dev, checks):
     """Precision form: BF16 operand iterations (18) + 2 FP32, on rank-200
     signal + noise, 8192 x 4096 and 4096 x 8192 (left-sided)."""
     from paper_2607_22484_amd import inputs
@@ -168,15 +172,17 @@ def precision_leg(psvt, torch, dev, check_oracle):
             row[name] = {"ms": ms, "matrices_per_s": 1e3 / ms,
                          "useful_tflops": useful_flops(m, n, 20) / (ms * 1e-3) / 1e12,
                          "mfma_util_by_dtype": {d: (f / (t * 1e-3) / 1e12) / peak[d] for d, (f, t) in mfma.items()}}
-            if check_oracle and m > n:
-                import oracle
-                ref = oracle.svt_gapped(pb.A, pb.tau, k=256)
-                row[name]["rel_err"] = oracle.rel_fro_err(Y.cpu().numpy().astype(np.float64), ref)
+            if checks is not None and m > n:
+                Yh = Y.cpu().numpy().astype(np.float64)
+
+                def check(oracle, pb=pb, Yh=Yh, dst=row[name]):
+                    dst["rel_err"] = oracle.rel_fro_err(Yh, oracle.svt_gapped(pb.A, pb.tau, k=256))
+                checks.append(check)
         out["%dx%d" % (m, n)] = row
     return out
 
 
-def batched_leg(psvt, torch, dev, check_oracle, count=512):
+def batched_leg(psvt, torch, dev, checks, count=512):
     """Batched form: 512 matrices, m, n log-uniform in [128, 2048], one graph
     launch per batch."""
     from paper_2607_22484_amd import inputs
@@ -190,13 +196,14 @@ def batched_leg(psvt, torch, dev, check_oracle, count=512):
         ms = time_calls(torch, b.run_graph, 3)
         row = {"ms_per_batch": ms, "matrices_per_s": count / (ms * 1e-3), "useful_tflops": fl / (ms * 1e-3) / 1e12,
                "launches_in_graph": nl}
-        if check_oracle:
-            import oracle
-            worst = 0.0
-            for p, Y in zip(pbs, b.Ys):
-                ref = oracle.svt_from_svd(p.U, p.sigma, p.V, p.tau)
-                worst = max(worst, oracle.rel_fro_err(Y.cpu().numpy().astype(np.float64), ref))
-            row["worst_rel_err"] = worst
+        if checks is not None:
+            Yh = [Y.cpu().numpy() for Y in b.Ys]
+
+            def check(oracle, Yh=Yh, dst=row):
+                dst["worst_rel_err"] = max(
+                    oracle.rel_fro_err(Y.astype(np.float64), oracle.svt_from_svd(p.U, p.sigma, p.V, p.tau))
+                    for p, Y in zip(pbs, Yh))
+            checks.append(check)
         out[name] = row
         b.close()
     # the plain FP32 form on the same matrices: one matrix per launch sequence
@@ -210,6 +217,41 @@ def batched_leg(psvt, torch, dev, check_oracle, count=512):
             psvt.svt(a, t, iters=20, out=y, ws=ws)
     ms = time_calls(torch, single, 1)
     out["fp32_single_calls"] = {"ms_per_batch": ms, "matrices_per_s": count / (ms * 1e-3)}
+    return out
+
+
+def fig1_leg(psvt, torch, dev, checks, taus=(1.0, 17.0, 33.0), kmax=30):
+    """Relative error against the number of polar iterations (the experiment
+    of Fig. 1): one i.i.d. Gaussian 301 x 300 matrix (singular values inside
+    the Marchenko-Pastur edges ~0.03 .. 34.7), tau near the bottom, middle
+    and top of the spectrum, 1..kmax iterations, four schedules: FP32, BF16
+    with the last 2 iterations FP32 (plain or split-bf16 P), and BF16
+    throughout (as the paper's experiment).  Errors are filled in by the CPU
+    oracle leg."""
+    from paper_2607_22484_amd import inputs
+    A = inputs.gaussian(301, 300, cfg=inputs.CFG_FIG1)
+    Ad = torch.from_numpy(A).to(dev)
+    scheds = {"fp32": lambda k: {}, "bf16_2fp32": lambda k: {"n_bf16": max(k - 2, 0)},
+              "bf16_splitP_2fp32": lambda k: {"n_bf16": max(k - 2, 0), "flags": psvt.FLAG_SPLIT_P},
+              "bf16": lambda k: {"n_bf16": k}}
+    outs = {}
+    t0 = time.perf_counter()
+    for name, kw in scheds.items():
+        for tau in taus:
+            outs[(name, tau)] = [psvt.svt(Ad, tau, iters=k, **kw(k)).cpu().numpy() for k in range(1, kmax + 1)]
+    torch.cuda.synchronize()
+    out = {"shape": [301, 300], "taus": list(taus), "iters": list(range(1, kmax + 1)),
+           "gpu_seconds_all_calls": time.perf_counter() - t0, "rel_err": {}}
+    if checks is not None:
+        def check(oracle, dst=out):
+            U, sv, V = oracle.svd(A)
+            dst["sigma_min_max"] = [float(sv[-1]), float(sv[0])]
+            dst["min_rel_gap"] = {str(t): float(np.min(np.abs(sv / t - 1.0))) for t in taus}
+            for (name, tau), Ys in outs.items():
+                ref = oracle.svt_from_svd(U, sv, V, tau)
+                dst["rel_err"].setdefault(name, {})[str(tau)] = [
+                    float("%.3g" % oracle.rel_fro_err(Y.astype(np.float64), ref)) for Y in Ys]
+        checks.append(check)
     return out
 
 
@@ -269,8 +311,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
-    ap.add_argument("--forms", default="precision,batched,serving",
-                    help="comma-separated subset of the precision / batched / serving legs to run")
+    ap.add_argument("--forms", default="precision,batched,serving,fig1",
+                    help="comma-separated subset of the precision / batched / serving / fig1 legs to run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
@@ -371,13 +413,8 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
-    if not args.no_cpu:
-        res = [y.cpu().numpy().astype(np.float64) for y in Y]
-        print("[bench] cpu oracle leg ...", file=sys.stderr, flush=True)
-        cpu, errs = cpu_baseline_leg(problems, res, args.cpu_sample)
-        out["cpu_baseline"] = cpu
-        out["accuracy"] = errs
-        out["rel_err_max"] = max(e["rel_err_bound_fp32_input"] for e in errs.values())
+    checks = None if args.no_cpu else []
+    res = None if args.no_cpu else [y.cpu().numpy().astype(np.float64) for y in Y]
     if not args.no_forms:
         del A, Y, ws
         torch.cuda.empty_cache()
@@ -385,15 +422,24 @@ def main():
         want = set(args.forms.split(","))
         if "precision" in want:
             print("[bench] precision form ...", file=sys.stderr, flush=True)
-            forms["precision"] = precision_leg(psvt, torch, dev, not args.no_cpu)
+            forms["precision"] = precision_leg(psvt, torch, dev, checks)
         if "batched" in want:
             print("[bench] batched form ...", file=sys.stderr, flush=True)
-            forms["batched"] = batched_leg(psvt, torch, dev, not args.no_cpu)
+            forms["batched"] = batched_leg(psvt, torch, dev, checks)
             torch.cuda.empty_cache()
         if "serving" in want:
             print("[bench] serving form ...", file=sys.stderr, flush=True)
             forms["serving"] = serving_leg(psvt, torch, dev)
+        if "fig1" in want:
+            print("[bench] error vs iterations (Fig. 1 workload) ...", file=sys.stderr, flush=True)
+            forms["fig1_error_vs_iterations"] = fig1_leg(psvt, torch, dev, checks)
         out["forms"] = forms
+    if not args.no_cpu:
+        print("[bench] cpu oracle leg (baseline timing and every accuracy figure) ...", file=sys.stderr, flush=True)
+        cpu, errs = cpu_baseline_leg(problems, res, args.cpu_sample, checks)
+        out["cpu_baseline"] = cpu
+        out["accuracy"] = errs
+        out["rel_err_max"] = max(e["rel_err_bound_fp32_input"] for e in errs.values())
     print(json.dumps(out), flush=True)
 
 
