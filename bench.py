@@ -317,8 +317,8 @@ def main():
                     help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (matrices are independent; "
-              "see the sharding note in the design document). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (matrices are independent, so "
+              "several GPUs would each take a share of them). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -162,16 +162,20 @@ int psvt_batch_destroy(psvt_batch *batch);
  * a worker thread.  Requests are admitted in arrival order while fewer than
  * `max_slots` are active and the pool has room for the request's workspace
  * (a request never overtakes an earlier one).  An admitted request's
- * iterates stay in its workspace on the device until it completes.  The
- * worker runs ticks: every active request advances by up to 3 stages of its
- * stage list; a round's stages are grouped by kind (products also by operand
- * type and tile configuration) into grouped launches, so requests at
- * different points of their iteration share launches and newcomers join at
- * the next tick (iteration-level continuous batching).  Tiles are computed
- * exactly as in single calls, so a result is the same alone and in the mix.
- * All requests use the server's psvt_config (its coeffs are copied).
- *   create:  allocates the pool and its stream; PSVT_SERVER_FAKE runs the
- *            scheduler without a device (stages complete at once; for tests).
+ * iterates stay in its workspace on the device until it completes.
+ * Admitted requests are split by size (s^2 l, s and l the short and long
+ * side) into four lanes.  The worker runs ticks per lane: every active
+ * request of the lane advances by up to 3 stages of its stage list; a
+ * round's stages are grouped by kind (products also by operand type and tile
+ * configuration) into grouped launches, so requests at different points of
+ * their iteration share launches and newcomers join at the next tick
+ * (iteration-level continuous batching).  Each lane has its own stream, so
+ * lanes overlap on the device.  Tiles are computed exactly as in single
+ * calls, so a result is the same alone and in the mix.  All requests use the
+ * server's psvt_config (its coeffs are copied).
+ *   create:  allocates the pool, the lanes' streams and descriptor rings;
+ *            PSVT_SERVER_FAKE runs the scheduler without a device (stages
+ *            complete at once; for tests).
  *   submit:  non-blocking; A is read and Y written by the device at some
  *            later time, so both must stay valid until the request is done.
  *            PSVT_EWORKSPACE if the request could never fit the budget.
