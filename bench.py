@@ -255,6 +255,44 @@ def fig1_leg(psvt, torch, dev, checks, taus=(1.0, 17.0, 33.0), kmax=30):
     return out
 
 
+def fig2_leg(psvt, torch, dev, checks, sizes=(1000, 2000, 3000, 4000, 5000), draws=5, iters=25):
+    """Run time against size (the experiment of Fig. 2, the polar method
+    only): i.i.d. Gaussian m x (m+1) matrices (left-sided), 25 iterations,
+    5 draws per size, tau = sqrt(m) (mid-spectrum: the singular values fill
+    [0, 2 sqrt(m)]); FP32, the BF16 schedule with split-bf16 P and 2 FP32
+    iterations, and BF16 throughout (as the paper's experiment).  Accuracy
+    of the first 1000 x 1001 draw is filled in by the CPU oracle leg."""
+    from paper_2607_22484_amd import inputs
+    scheds = {"fp32": {}, "bf16_splitP_2fp32": {"n_bf16": iters - 2, "flags": psvt.FLAG_SPLIT_P},
+              "bf16": {"n_bf16": iters}}
+    out = {"iters": iters, "draws": draws, "ms_per_svt": {}}
+    keep = {}
+    for m in sizes:
+        As = [torch.from_numpy(inputs.gaussian(m, m + 1, cfg=inputs.CFG_FIG2, idx=d)).to(dev) for d in range(draws)]
+        tau = math.sqrt(m)
+        Y = torch.empty_like(As[0])
+        for name, kw in scheds.items():
+            cfg, _ = psvt.make_config(iters=iters, **kw)
+            ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, m, m + 1, cfg), dtype=torch.uint8, device=dev)
+            ms = [time_calls(torch, lambda A=A: psvt.svt(A, tau, iters=iters, out=Y, ws=ws, **kw), 1) for A in As]
+            out["ms_per_svt"].setdefault(name, {})[str(m)] = float(np.mean(ms))
+            if m == sizes[0]:
+                psvt.svt(As[0], tau, iters=iters, out=Y, ws=ws, **kw)
+                keep[name] = Y.cpu().numpy().astype(np.float64)
+            del ws
+        if m == sizes[0]:
+            keep["A"] = As[0].cpu().numpy()
+            keep["tau"] = tau
+        del As, Y
+    if checks is not None:
+        def check(oracle, dst=out):
+            ref = oracle.svt(keep["A"], keep["tau"])
+            dst["rel_err_%dx%d" % (sizes[0], sizes[0] + 1)] = {
+                name: oracle.rel_fro_err(keep[name], ref) for name in scheds}
+        checks.append(check)
+    return out
+
+
 def serving_leg(psvt, torch, dev, rates=(200, 1000, 5000), count=300):
     """Serving form: Poisson arrivals, sizes 256..4096 square and 2:1, rank
     r in {16, 64, 256} + noise, 6 FP8 + 12 BF16 + 2 FP32 iterations."""
@@ -311,8 +349,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
-    ap.add_argument("--forms", default="precision,batched,serving,fig1",
-                    help="comma-separated subset of the precision / batched / serving / fig1 legs to run")
+    ap.add_argument("--forms", default="precision,batched,serving,fig1,fig2",
+                    help="comma-separated subset of the precision / batched / serving / fig1 / fig2 legs to run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
@@ -433,6 +471,9 @@ def main():
         if "fig1" in want:
             print("[bench] error vs iterations (Fig. 1 workload) ...", file=sys.stderr, flush=True)
             forms["fig1_error_vs_iterations"] = fig1_leg(psvt, torch, dev, checks)
+        if "fig2" in want:
+            print("[bench] run time vs size (Fig. 2 workload) ...", file=sys.stderr, flush=True)
+            forms["fig2_time_vs_size"] = fig2_leg(psvt, torch, dev, checks)
         out["forms"] = forms
     if not args.no_cpu:
         print("[bench] cpu oracle leg (baseline timing and every accuracy figure) ...", file=sys.stderr, flush=True)
