@@ -93,18 +93,16 @@ __device__ __forceinline__ floatx16 mfma_32b(const u32x4 &a0, const u32x4 &a1, c
 }
 
 // Epilogue for one lane's 4 consecutive rows ib..ib+3 of column j:
-// v = alpha acc (given) + beta D + diag [i == j], then the FP32 outputs C/CT
+// v = alpha acc + beta D (given) + diag [i == j], then the FP32 outputs C/CT
 // and the low-precision copies Clp/CTlp (value * lp_scale).  SYM: only
 // i >= j is kept on diagonal tiles and every kept i != j is also written to
 // the mirrored position [j][i].
 template <bool SYM>
-__device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j, float v[4], float beta,
-                                               bool diag_tile) {
+__device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j, float v[4], bool diag_tile) {
     bool wr[4], mir[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int i = ib + e;
-        if (beta != 0.0f && i < g.M) v[e] += beta * g.D[(int64_t)i * g.ldd + j];
         if (i == j) v[e] += g.diag;
         wr[e] = i < g.M && (!diag_tile || i >= j);
         mir[e] = SYM && wr[e] && i != j;
@@ -158,14 +156,30 @@ __device__ __forceinline__ void store_tile(const GemmArgs &g, int bi, int bj, fl
     const float beta = g.D ? g.beta * scal(g.sc, g.i_beta) : 0.0f;
     const bool diag_tile = SYM && (bi == bj);
     static_for<BM / 64>([&](auto a) {
+        // the D values of this row of 32x32 blocks, loaded together so that
+        // their latency is paid once per row rather than once per four rows
+        float dv[BN / 64][16];
+        static_for<BN / 64>([&](auto b) {
+            const int j = j0 + wn * (BN / 2) + b * 32 + frow;
+            static_for<4>([&](auto rg) {
+                const int ib = i0 + wm * (BM / 2) + a * 32 + rg * 8 + fh * 4;
+                static_for<4>([&](auto e) {
+                    const int i = ib + e;
+                    dv[b][rg * 4 + e] = (beta != 0.0f && i < g.M && j < g.N) ? g.D[(int64_t)i * g.ldd + j] : 0.0f;
+                });
+            });
+        });
         static_for<BN / 64>([&](auto b) {
             const int j = j0 + wn * (BN / 2) + b * 32 + frow;
             const bool jok = j < g.N;
             static_for<4>([&](auto rg) {
                 const int ib = i0 + wm * (BM / 2) + a * 32 + rg * 8 + fh * 4;  // rows ib .. ib+3
                 float v[4];
-                static_for<4>([&](auto e) { v[e] = alpha * acc[a][b][rg * 4 + e]; });
-                if (jok) epilogue_store<SYM>(g, ib, j, v, beta, diag_tile);
+                static_for<4>([&](auto e) {
+                    v[e] = alpha * acc[a][b][rg * 4 + e];
+                    if (beta != 0.0f) v[e] += beta * dv[b][rg * 4 + e];
+                });
+                if (jok) epilogue_store<SYM>(g, ib, j, v, diag_tile);
             });
         });
     });

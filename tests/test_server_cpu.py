@@ -43,18 +43,20 @@ def test_mixed_sizes_over_all_lanes():
     srv.close()
 
 
-def test_budget_limits_concurrency():
-    """With room for exactly two requests at a time, peak pool use never
-    exceeds the budget and every request still completes."""
+@pytest.mark.parametrize("room", [1, 2])
+def test_budget_limits_concurrency(room):
+    """With room for exactly one or two requests at a time, peak pool use
+    never exceeds the budget and every request still completes.  (The fake
+    executor finishes stages at once, so how many requests overlap depends
+    on thread timing; only the upper bound is deterministic.)"""
     need = psvt.workspace_bytes(psvt.OP_SVT, 256, 256)
-    budget = 2 * ((need + 255) // 256 * 256) + 1024
+    budget = room * ((need + 255) // 256 * 256) + 1024
     srv = psvt.Server(budget_bytes=budget, max_slots=16, fake=True)
     tickets = [submit(srv, 256, 256) for _ in range(10)]
     srv.drain(timeout=30)
     st = srv.stats()
     assert st["completed"] == 10
-    assert st["peak_bytes"] <= budget
-    assert st["peak_bytes"] >= 2 * need
+    assert need <= st["peak_bytes"] <= budget
     assert all(srv.poll(t) == psvt.RQ_DONE for t in tickets)
     srv.close()
 
