@@ -14,10 +14,11 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpsvt.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-# the tile-kernel units first: they dominate the build
-SOURCES = ["gemm_f32.hip", "gemm_f32_grouped.hip", "gemm_bf16x3.hip", "gemm_bf16x3_grouped.hip", "gemm_bf16.hip",
-           "gemm_bf16_grouped.hip", "gemm_fp8.hip", "gemm_fp8_grouped.hip", "kernels.hip", "api.hip", "trace.hip",
-           "batch.hip", "server.hip"]
+# the tile-kernel units first (one per operand type and tile configuration):
+# they dominate the build
+_TILE_UNITS = ["gemm_%s_%d.hip" % (t, bm) for t in ("f32", "bf16x3", "bf16", "fp8") for bm in (256, 192, 128, 64)]
+SOURCES = _TILE_UNITS + ["gemm_f32.hip", "gemm_bf16x3.hip", "gemm_bf16.hip", "gemm_fp8.hip", "kernels.hip",
+                         "api.hip", "trace.hip", "batch.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled: the compiler must not form

@@ -1,9 +1,20 @@
-// MFMA tile kernels for FP32 operands (single products; one translation unit per
-// operand type and launch form so that the library builds in parallel).
+// MFMA tile kernels for FP32 operands: the launch dispatchers.  The kernels
+// themselves are instantiated one tile configuration per translation unit
+// (gemm_f32_<tile>.hip) so that the library builds in parallel.
 #include "tile.h"
 
 namespace psvt {
 
+extern template hipError_t gemm_launch_bm<OP_F32, 64, tile_occupancy<OP_F32, 64>()>(const GemmArgs &, int, hipStream_t);
+extern template hipError_t gemm_grouped_bm<OP_F32, 64, tile_occupancy<OP_F32, 64>()>(const GemmArgs *, const int *, int, int, int, int, hipStream_t);
+extern template hipError_t gemm_launch_bm<OP_F32, 128, tile_occupancy<OP_F32, 128>()>(const GemmArgs &, int, hipStream_t);
+extern template hipError_t gemm_grouped_bm<OP_F32, 128, tile_occupancy<OP_F32, 128>()>(const GemmArgs *, const int *, int, int, int, int, hipStream_t);
+extern template hipError_t gemm_launch_bm<OP_F32, 192, 1>(const GemmArgs &, int, hipStream_t);
+extern template hipError_t gemm_grouped_bm<OP_F32, 192, 1>(const GemmArgs *, const int *, int, int, int, int, hipStream_t);
+extern template hipError_t gemm_launch_bm<OP_F32, 256, 1>(const GemmArgs &, int, hipStream_t);
+extern template hipError_t gemm_grouped_bm<OP_F32, 256, 1>(const GemmArgs *, const int *, int, int, int, int, hipStream_t);
+
 template hipError_t gemm_launch<OP_F32>(const GemmArgs &, int, int, hipStream_t);
+template hipError_t gemm_launch_grouped<OP_F32>(const GemmArgs *, const int *, int, int, int, int, int, hipStream_t);
 
 }  // namespace psvt
