@@ -143,9 +143,10 @@ def time_calls(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def precision_leg(psvt, torch, dev, checks):
+def precision_leg(psvt, torch, dev, checks, problems=None):
     """Precision form: BF16 operand iterations (18) + 2 FP32, on rank-200
-    signal + noise, 8192 x 4096 and 4096 x 8192 (left-sided)."""
+    signal + noise, 8192 x 4096 and 4096 x 8192 (left-sided); beside it
+    FP32 and all 20 iterations in split bf16 (no FP32 refinement)."""
     from paper_2607_22484_amd import inputs
     out = {}
     for (m, n) in [(8192, 4096), (4096, 8192)]:
@@ -153,7 +154,8 @@ def precision_leg(psvt, torch, dev, checks):
         A = torch.from_numpy(pb.A).to(dev)
         Y = torch.empty_like(A)
         row = {}
-        for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18))]:
+        for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)),
+                         ("split_bf16_all", dict(n_bf16=20, flags=psvt.FLAG_SPLIT_P))]:
             cfg, _ = psvt.make_config(iters=20, **kw)
             ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, m, n, cfg), dtype=torch.uint8, device=dev)
             ms = time_calls(torch, lambda: psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw), 3)
@@ -179,6 +181,39 @@ def precision_leg(psvt, torch, dev, checks):
                     dst["rel_err"] = oracle.rel_fro_err(Yh, oracle.svt_gapped(pb.A, pb.tau, k=256))
                 checks.append(check)
         out["%dx%d" % (m, n)] = row
+    # the main workload (three 4096^2 constructed matrices, tau at the 10/50/90 %
+    # quantiles) under the low-precision schedules
+    if problems:
+        As = [torch.from_numpy(pb.A).to(dev) for pb in problems]
+        Y = torch.empty_like(As[0])
+        row = {}
+        for name, kw in [("bf16_splitP", dict(n_bf16=18, flags=psvt.FLAG_SPLIT_P)),
+                         ("split_bf16_all", dict(n_bf16=20, flags=psvt.FLAG_SPLIT_P))]:
+            cfg, _ = psvt.make_config(iters=20, **kw)
+            ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, *problems[0].A.shape, cfg), dtype=torch.uint8, device=dev)
+
+            def three(kw=kw, ws=ws):
+                for A, pb in zip(As, problems):
+                    psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw)
+            ms = time_calls(torch, three, 2)
+            row[name] = {"ms_per_matrix": ms / len(As), "matrices_per_s": 1e3 * len(As) / ms}
+            if checks is not None:
+                Ys = []
+                for A, pb in zip(As, problems):
+                    psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw)
+                    Ys.append(Y.cpu().numpy().astype(np.float64))
+
+                def check(oracle, Ys=Ys, dst=row[name]):
+                    worst = 0.0
+                    for pb, Yh in zip(problems, Ys):
+                        ref = oracle.svt_from_svd(pb.U, pb.sigma, pb.V, pb.tau)
+                        delta = float(np.linalg.norm(pb.A.astype(np.float64) - pb.A64))
+                        worst = max(worst, (np.linalg.norm(Yh - ref) + delta) / (np.linalg.norm(ref) - delta))
+                    dst["worst_rel_err_bound_fp32_input"] = float(worst)
+                checks.append(check)
+            del ws
+        out["main_workload_%dx%d" % problems[0].A.shape] = row
+        del As, Y
     return out
 
 
@@ -460,7 +495,7 @@ def main():
         want = set(args.forms.split(","))
         if "precision" in want:
             print("[bench] precision form ...", file=sys.stderr, flush=True)
-            forms["precision"] = precision_leg(psvt, torch, dev, checks)
+            forms["precision"] = precision_leg(psvt, torch, dev, checks, problems)
         if "batched" in want:
             print("[bench] batched form ...", file=sys.stderr, flush=True)
             forms["batched"] = batched_leg(psvt, torch, dev, checks)
