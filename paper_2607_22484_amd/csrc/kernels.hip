@@ -1,9 +1,9 @@
 // gfx950 (CDNA4) host launchers and the small kernels of the method:
 // tile-configuration choice and cost model for the MFMA products (whose
-// device code lives in tile.h and is instantiated per operand type in
-// gemm_<type>.hip), Frobenius norms with FP64 accumulation, and the
-// element-wise tile operations (scaling, transposition, shifts, conversion
-// to the low-precision operand formats).
+// device code lives in tile.h and is instantiated one operand type and tile
+// configuration per unit in gemm_<type>_<tile>.hip), Frobenius norms with
+// FP64 accumulation, and the element-wise tile operations (scaling,
+// transposition, shifts, conversion to the low-precision operand formats).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -26,7 +26,7 @@ struct TileCfg {
 static const TileCfg kTiles[] = {{0, 0, ""}, {64, 4, "64"}, {128, 2, "128"}, {192, 1, "192"}, {256, 1, "256"}};
 constexpr int kNumTiles = 4;
 static const char *kTypeTag[4] = {"f32", "bf16", "fp8", "bf16x3"};
-// dense MFMA flop/s of one CU per operand type (257 = 256 CUs + 1)
+// dense MFMA flop/s of one CU per operand type
 // (split bf16: the useful rate, a third of bf16's, since every product takes three)
 static const double kCuRate[4] = {157.3e12 / 256.0, 2516.6e12 / 256.0, 5033.2e12 / 256.0, 2516.6e12 / 3.0 / 256.0};
 

@@ -1,6 +1,7 @@
 // Device code of the MFMA tile kernel shared by every product of the method
-// (included by the per-operand-type translation units and, for its operand
-// helpers, by kernels.hip).
+// (included by the units gemm_<type>_<tile>.hip, which instantiate one
+// operand type and tile configuration each, and gemm_<type>.hip, which
+// instantiate the dispatchers).
 //
 // The hot path is a chain of dense products (the polar iterations of
 // sections 1-2 of the paper, and the fused form of Proposition 1).  They all
@@ -587,7 +588,8 @@ __global__ __launch_bounds__(256, OCC) void gemm_grouped(const GemmArgs *args, c
 }
 
 // ------------------------------------------------------------ launchers
-// Instantiated once per operand type, each in its own translation unit.
+// Launchers of one tile configuration (instantiated one operand type and
+// configuration per translation unit) and the dispatchers over them.
 
 template <int ET, int BM, int OCC>
 hipError_t gemm_launch_bm(const GemmArgs &g, int nblocks, hipStream_t st) {
