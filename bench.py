@@ -255,6 +255,31 @@ def batched_leg(psvt, torch, dev, checks, count=512):
     return out
 
 
+def small_leg(psvt, torch, dev, checks, reps=50):
+    """The small case (256 x 128 constructed, tau = 0.1, 20 FP32 iterations):
+    latency of one SVT from eager launches and from a one-item batch graph
+    (the same kernels, one submission)."""
+    from paper_2607_22484_amd import inputs
+    pb = inputs.small_case()
+    A = torch.from_numpy(pb.A).to(dev)
+    Y = torch.empty_like(A)
+    cfg, _ = psvt.make_config(iters=20)
+    ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, *pb.A.shape, cfg), dtype=torch.uint8, device=dev)
+    eager_ms = time_calls(torch, lambda: psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws), reps)
+    b = psvt.Batch([A], [pb.tau], iters=20)
+    graph_ms = time_calls(torch, b.run_graph, reps)
+    nl, _ = b.stats()
+    out = {"shape": list(pb.A.shape), "eager_us": 1e3 * eager_ms, "graph_us": 1e3 * graph_ms, "launches": nl}
+    if checks is not None:
+        Yh = b.Ys[0].cpu().numpy().astype(np.float64)
+
+        def check(oracle, dst=out):
+            dst["rel_err"] = oracle.rel_fro_err(Yh, oracle.svt(pb.A, pb.tau))
+        checks.append(check)
+    b.close()
+    return out
+
+
 def fig1_leg(psvt, torch, dev, checks, taus=(1.0, 17.0, 33.0), kmax=30):
     """Relative error against the number of polar iterations (the experiment
     of Fig. 1): one i.i.d. Gaussian 301 x 300 matrix (singular values inside
@@ -384,8 +409,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
-    ap.add_argument("--forms", default="precision,batched,serving,fig1,fig2",
-                    help="comma-separated subset of the precision / batched / serving / fig1 / fig2 legs to run")
+    ap.add_argument("--forms", default="small,precision,batched,serving,fig1,fig2",
+                    help="comma-separated subset of the small / precision / batched / serving / fig1 / fig2 legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
@@ -493,6 +518,9 @@ def main():
         torch.cuda.empty_cache()
         forms = {}
         want = set(args.forms.split(","))
+        if "small" in want:
+            print("[bench] small case latency ...", file=sys.stderr, flush=True)
+            forms["small_256x128"] = small_leg(psvt, torch, dev, checks)
         if "precision" in want:
             print("[bench] precision form ...", file=sys.stderr, flush=True)
             forms["precision"] = precision_leg(psvt, torch, dev, checks, problems)
