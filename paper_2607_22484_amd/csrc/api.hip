@@ -671,15 +671,59 @@ int check_ws(void *ws, size_t ws_bytes, const Layout &L) {
 }
 
 // The stage list of svt / rank_r (Proposition 1 / Corollary 1).
+// A library-owned second stream per (host thread, device) and the two events
+// of a fork/join with the caller's stream.  Created on first use, kept for
+// the life of the thread (default priority, non-blocking).
+struct SideStream {
+    hipStream_t st = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    bool failed = false;
+};
+SideStream *side_stream() {
+    static thread_local SideStream sides[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    SideStream &s = sides[dev];
+    if (s.failed) return nullptr;
+    if (!s.st) {
+        if (hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s.join, hipEventDisableTiming) != hipSuccess) {
+            s.failed = true;
+            return nullptr;
+        }
+    }
+    return &s;
+}
+
+// P and S are independent once the Gram and the shifted Gram exist.  When a
+// single call's products are too small to fill the device (s <= 2048) and the
+// schedule is plain FP32 (P and S then share no buffer), the P iterations run
+// on the side stream, forked from and joined back into the caller's stream
+// before the final product.
+constexpr int64_t kForkMaxS = 2048;
+
 int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
                   void *ws, const Layout &L, const Cfg &c, Exec &ex) {
     int rc;
     if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, op == PSVT_OP_SVT))) return rc;
     if ((rc = shifted_gram(L, ws, ex))) return rc;
     const float *P = nullptr, *Pi = nullptr;
+    SideStream *side = nullptr;
+    if (op == PSVT_OP_SVT && !ex.rec && !L.lp && L.s <= kForkMaxS && (side = side_stream())) {
+        HIP_TRY(hipEventRecord(side->fork, ex.st), "fork");
+        HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0), "fork");
+    }
+    Exec exP;
+    exP.st = side ? side->st : ex.st;
+    exP.rec = ex.rec;
     if (op == PSVT_OP_SVT)
-        if ((rc = polar_iterations(c, L, ws, ex, nullptr, 0, &P))) return rc;
+        if ((rc = polar_iterations(c, L, ws, exP, nullptr, 0, &P))) return rc;
     if ((rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi))) return rc;
+    if (side) {
+        HIP_TRY(hipEventRecord(side->join, side->st), "join");
+        HIP_TRY(hipStreamWaitEvent(ex.st, side->join, 0), "join");
+    }
     return final_product(L, ws, P, tau, Pi, Y, ldy, ex);
 }
 
