@@ -179,7 +179,19 @@ struct GroupKey {
     }
 };
 
-int launch_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *> &reqs, int seg, size_t &seg_used) {
+// One grouped launch of a round: descriptors at `off` in the segment, the
+// tile prefix after them.
+struct Group {
+    GroupKey k;
+    size_t off;
+    int n, total;
+    double flops, bytes;
+};
+
+// Host side of one round: the groups' descriptors into the segment (after
+// seg_used), the requests' cursors advanced; the launches are appended to gl.
+int build_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *> &reqs, int seg, size_t &seg_used,
+                std::vector<Group> &gl) {
     std::map<GroupKey, std::vector<Request *>> groups;
     for (Request *r : reqs) {
         const Stage &st = r->plan[r->cursor];
@@ -189,16 +201,8 @@ int launch_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *>
         groups[k].push_back(r);
     }
     char *hseg = lane.ring_host + (size_t)seg * psvt_server::kSegBytes;
-    char *dseg = lane.ring_dev + (size_t)seg * psvt_server::kSegBytes;
-    struct Group {
-        GroupKey k;
-        size_t off;  // descriptors at off, prefix after them
-        int n, total;
-        double flops, bytes;
-    };
-    std::vector<Group> gl;
-    const size_t round_start = seg_used;
-    // host: every group's descriptors into this round's part of the segment
+    const size_t first = gl.size();
+    // every group's descriptors into this round's part of the segment
     for (auto &kv : groups) {
         const GroupKey &k = kv.first;
         auto &rs = kv.second;
@@ -232,12 +236,18 @@ int launch_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *>
         seg_used += need;
         gl.push_back(G);
     }
-    s->launches += (int64_t)gl.size();
+    s->launches += (int64_t)(gl.size() - first);
     for (Request *r : reqs) r->cursor++;
+    return PSVT_OK;
+}
+
+// Device side of one tick: one descriptor copy for all its rounds, then the
+// rounds' launches in order on the lane's stream.
+int launch_tick(psvt_server *s, psvt_server::Lane &lane, int seg, size_t seg_used, const std::vector<Group> &gl) {
     if (s->fake || gl.empty()) return PSVT_OK;
-    // device: one descriptor copy, then the groups, on the lane's stream
-    hipError_t e = hipMemcpyAsync(dseg + round_start, hseg + round_start, seg_used - round_start,
-                                  hipMemcpyHostToDevice, lane.stream);
+    char *hseg = lane.ring_host + (size_t)seg * psvt_server::kSegBytes;
+    char *dseg = lane.ring_dev + (size_t)seg * psvt_server::kSegBytes;
+    hipError_t e = hipMemcpyAsync(dseg, hseg, seg_used, hipMemcpyHostToDevice, lane.stream);
     for (size_t gi = 0; gi < gl.size() && e == hipSuccess; ++gi) {
         const Group &G = gl[gi];
         const GroupKey &k = G.k;
@@ -337,13 +347,15 @@ void worker_main(psvt_server *s) {
             if (!s->fake && ln.seg_tick[seg] >= 0 && hipEventQuery(ln.seg_event[seg]) != hipSuccess) continue;
             size_t seg_used = 0;
             int rc = PSVT_OK;
+            std::vector<Group> gl;
             for (int round = 0; round < s->rounds && rc == PSVT_OK; ++round) {
                 std::vector<Request *> rr;
                 for (Request *r : runnable)
                     if (r->cursor < r->plan.size()) rr.push_back(r);
                 if (rr.empty()) break;
-                rc = launch_round(s, ln, rr, seg, seg_used);
+                rc = build_round(s, ln, rr, seg, seg_used, gl);
             }
+            if (rc == PSVT_OK) rc = launch_tick(s, ln, seg, seg_used, gl);
             if (!s->fake) {
                 (void)hipEventRecord(ln.seg_event[seg], ln.stream);
                 ln.seg_tick[seg] = ln.tick;
