@@ -23,10 +23,10 @@
  *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only
  *     enqueues work on `stream` and returns: no host synchronisation, no device
  *     allocation, no device-to-host read.  Results are ready when the stream
- *     reaches that point.  (psvt_svt with a plain FP32 schedule and
- *     min(m, n) <= 2048 runs the polar iterations of P on a library-owned
- *     side stream of the calling thread, forked from `stream` and joined back
- *     into it by events before the final product.)
+ *     reaches that point.  (psvt_svt with min(m, n) <= 2048 runs the polar
+ *     iterations of P on a library-owned side stream of the calling thread,
+ *     forked from `stream` and joined back into it by events before the
+ *     final product.)
  *   - `ws` is caller-owned device scratch of at least psvt_workspace_bytes()
  *     bytes, 256-byte aligned; its contents need not be initialised and are
  *     garbage afterwards.  Calls that overlap in time must not share `ws`.

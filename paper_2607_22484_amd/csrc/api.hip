@@ -203,6 +203,10 @@ struct Layout {
     // (split bf16); plane strides in elements
     bool lp = false;
     size_t XL[2] = {0, 0}, XTL[2] = {0, 0}, TL = 0, BL = 0, SL[2] = {0, 0};
+    // S's copies of X^2 and B: the same buffers as P's unless the two
+    // iterations run concurrently (fork)
+    size_t X2L = 0, BSL = 0;
+    bool fork = false;
     int64_t planeX = 0, planeXT = 0, planeS = 0;
     size_t total = 0;
 };
@@ -214,7 +218,16 @@ bool choose_right(int side, int64_t m, int64_t n) {
     return n < m;
 }
 
-Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c) {
+// P and S are independent once the Gram and the shifted Gram exist.  When a
+// single call's products are too small to fill the device (s <= 2048), the P
+// iterations run on a side stream, forked from and joined back into the
+// caller's stream before the final product; the layout then gives S its own
+// low-precision copies of X^2 and B.
+constexpr int64_t kForkMaxS = 2048;
+
+// single: a stand-alone call on its own stream (not a batch item or a served
+// request, whose stages are recorded and replayed in one stream)
+Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c, bool single = false) {
     Layout L;
     if (op == PSVT_OP_POLAR_SYM) {
         L.right = true;
@@ -268,6 +281,8 @@ Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c) {
     if (L.lp) {
         L.TL = take(fS);
         L.BL = take(fS);
+        L.X2L = L.TL;
+        L.BSL = L.BL;
         if (need_P)
             for (int i = 0; i < 2; ++i) {
                 L.XL[i] = take(fX);
@@ -278,6 +293,11 @@ Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c) {
         L.planeX = L.l * L.ldS;
         L.planeXT = L.s * L.ldL;
         L.planeS = L.s * L.ldS;
+    }
+    L.fork = single && op == PSVT_OP_SVT && L.s <= kForkMaxS;
+    if (L.fork && L.lp) {
+        L.X2L = take(fS);
+        L.BSL = take(fS);
     }
     L.total = off;
     return L;
@@ -530,7 +550,7 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, bool want
     float *R = F(ws, L.R), *X2 = F(ws, L.X2), *BS = F(ws, L.BS);
     float *buf[2] = {F(ws, L.S0), F(ws, L.S1)};
     void *buflp[2] = {L.lp ? at(ws, L.SL[0]) : nullptr, L.lp ? at(ws, L.SL[1]) : nullptr};
-    void *X2lp = L.lp ? at(ws, L.TL) : nullptr, *BSlp = L.lp ? at(ws, L.BL) : nullptr;
+    void *X2lp = L.lp ? at(ws, L.X2L) : nullptr, *BSlp = L.lp ? at(ws, L.BSL) : nullptr;
     for (int t = 0; t < c.iters; ++t) {
         float a, b, cc;
         coef(c, t, a, b, cc);
@@ -696,13 +716,6 @@ SideStream *side_stream() {
     return &s;
 }
 
-// P and S are independent once the Gram and the shifted Gram exist.  When a
-// single call's products are too small to fill the device (s <= 2048) and the
-// schedule is plain FP32 (P and S then share no buffer), the P iterations run
-// on the side stream, forked from and joined back into the caller's stream
-// before the final product.
-constexpr int64_t kForkMaxS = 2048;
-
 int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
                   void *ws, const Layout &L, const Cfg &c, Exec &ex) {
     int rc;
@@ -710,7 +723,7 @@ int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, dou
     if ((rc = shifted_gram(L, ws, ex))) return rc;
     const float *P = nullptr, *Pi = nullptr;
     SideStream *side = nullptr;
-    if (op == PSVT_OP_SVT && !ex.rec && !L.lp && L.s <= kForkMaxS && (side = side_stream())) {
+    if (L.fork && !ex.rec && (side = side_stream())) {
         HIP_TRY(hipEventRecord(side->fork, ex.st), "fork");
         HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0), "fork");
     }
@@ -737,7 +750,7 @@ int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double t
     if ((rc = check_matrix(Y, m, n, ldy, "Y"))) return rc;
     if (!(tau >= 0.0) || !isfinite(tau)) return fail(PSVT_EINVAL, "tau must be finite and >= 0");
     if (m == 0 || n == 0) return PSVT_OK;
-    Layout L = make_layout(op, m, n, c);
+    Layout L = make_layout(op, m, n, c, true);
     if ((rc = check_ws(ws, ws_bytes, L))) return rc;
     if (overlaps(Y, span_bytes(m, n, ldy), A, span_bytes(m, n, lda)) ||
         overlaps(Y, span_bytes(m, n, ldy), ws, L.total) || overlaps(A, span_bytes(m, n, lda), ws, L.total))
@@ -792,7 +805,7 @@ int psvt_workspace_bytes(int op, int64_t m, int64_t n, const psvt_config *cfg, s
         *bytes = 0;
         return PSVT_OK;
     }
-    *bytes = make_layout(op, m, n, c).total;
+    *bytes = make_layout(op, m, n, c, true).total;
     return PSVT_OK;
 }
 
