@@ -730,13 +730,15 @@ int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, dou
     Exec exP;
     exP.st = side ? side->st : ex.st;
     exP.rec = ex.rec;
-    if (op == PSVT_OP_SVT)
-        if ((rc = polar_iterations(c, L, ws, exP, nullptr, 0, &P))) return rc;
-    if ((rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi))) return rc;
+    if (op == PSVT_OP_SVT) rc = polar_iterations(c, L, ws, exP, nullptr, 0, &P);
+    if (!rc) rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi);
     if (side) {
+        // joined on failure too: after an error the caller may free ws as
+        // soon as its own stream is done, so no side-stream work may remain
         HIP_TRY(hipEventRecord(side->join, side->st), "join");
         HIP_TRY(hipStreamWaitEvent(ex.st, side->join, 0), "join");
     }
+    if (rc) return rc;
     return final_product(L, ws, P, tau, Pi, Y, ldy, ex);
 }
 
