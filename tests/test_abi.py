@@ -47,6 +47,30 @@ def test_workspace_bytes():
         psvt.workspace_bytes(9, 5, 6)
 
 
+def batch_ws(m, n, cfg):
+    lib = psvt.load()
+    items = (psvt.BatchItem * 1)()
+    items[0] = psvt.BatchItem(1 << 40, 1 << 41, m, n, n, n, 0.5)
+    out = ctypes.c_size_t(0)
+    assert lib.psvt_batch_workspace_bytes(psvt.OP_SVT, items, 1, ctypes.byref(cfg), ctypes.byref(out)) == 0
+    return out.value
+
+
+@pytest.mark.parametrize("m,n", [(300, 200), (2048, 3000), (3000, 2049)])
+def test_workspace_fork_copies(m, n):
+    """A single low-precision call with min(m, n) <= 2048 runs P's iterations
+    on a side stream and needs two more s x s copies (X^2 and B of S); batch
+    items, FP32 schedules and larger s share them."""
+    s = min(m, n)
+    ld = -(-s // 64) * 64
+    extra = 2 * (-(-4 * s * ld // 256) * 256)
+    fp32, _ = psvt.make_config(iters=20)
+    bf16, _ = psvt.make_config(iters=20, n_bf16=18)
+    assert psvt.workspace_bytes(psvt.OP_SVT, m, n, fp32) == batch_ws(m, n, fp32)
+    fork = s <= 2048
+    assert psvt.workspace_bytes(psvt.OP_SVT, m, n, bf16) == batch_ws(m, n, bf16) + (extra if fork else 0)
+
+
 FAKE = ctypes.c_void_p(1 << 40)  # never dereferenced: every call below fails validation first
 
 
