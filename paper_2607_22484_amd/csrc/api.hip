@@ -171,11 +171,12 @@ float pow2_scale(double bound) {
 // U_t bounds the singular values entering iteration t (U_0 = 1 after the
 // theta normalisation); B_t's eigenvalues are b mu + c mu^2 over
 // mu in [0, U_t^2]; the quintic maps [0, U_t] into [-U_{t+1}, U_{t+1}].
-void iteration_scales(const Cfg &c, IterScale *out) {
+// Entry t depends on the coefficients of iterations 0..t only.
+void scales_from(const Cfg &c, int count, IterScale *out) {
     double U = 1.0;
-    for (int t = 0; t <= c.iters; ++t) {
-        float a = 1.875f, b = -1.25f, cc = 0.375f;
-        if (t < c.iters) coef(c, t, a, b, cc);
+    for (int t = 0; t < count; ++t) {
+        float a, b, cc;
+        coef(c, t, a, b, cc);
         double beta = 0.0, unext = 0.0;
         const int n = 4096;
         for (int k = 0; k <= n; ++k) {
@@ -186,6 +187,28 @@ void iteration_scales(const Cfg &c, IterScale *out) {
         out[t] = IterScale{pow2_scale(U), pow2_scale(U * U), pow2_scale(beta)};
         U = fmax(unext, 1e-30);
     }
+}
+
+// Scales of the FP8 iterations (entries 0 .. n_fp8 - 1; nothing else reads
+// them).  The bound takes 4097 polynomial evaluations per iteration, so the
+// built-in schedule's entries are computed once and kept; a caller-supplied
+// schedule is evaluated on every call.
+void iteration_scales(const Cfg &c, IterScale *out) {
+    const int count = c.n_fp8 < c.iters ? c.n_fp8 : c.iters;
+    if (count <= 0) return;
+    if (c.coeffs) {
+        scales_from(c, count, out);
+        return;
+    }
+    static std::mutex mu;
+    static IterScale cache[256];
+    static int have = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (have < count) {
+        scales_from(c, count, cache);
+        have = count;
+    }
+    memcpy(out, cache, sizeof(IterScale) * (size_t)count);
 }
 
 // ---------------------------------------------------------- workspace
