@@ -280,6 +280,30 @@ def small_leg(psvt, torch, dev, checks, reps=50):
     return out
 
 
+def rank_leg(psvt, torch, dev, checks, n=4096, r=256, reps=3):
+    """Corollary 1 on the main workload's recipe: the best rank-r
+    approximation [A]_r = A (I + S)/2 of a 4096^2 matrix (no polar factor),
+    r = 256, tau between sigma_256 and sigma_257, plain FP32, 20 iterations."""
+    from paper_2607_22484_amd import inputs
+    pb = inputs.rank_case(r=r, n=n)
+    A = torch.from_numpy(pb.A).to(dev)
+    Y = torch.empty_like(A)
+    cfg, _ = psvt.make_config(iters=20)
+    ws = torch.empty(psvt.workspace_bytes(psvt.OP_RANK_R, n, n, cfg), dtype=torch.uint8, device=dev)
+    ms = time_calls(torch, lambda: psvt.rank_r(A, pb.tau, iters=20, out=Y, ws=ws), reps)
+    row = {"shape": [n, n], "r": r, "ms": ms, "matrices_per_s": 1e3 / ms,
+           "useful_tflops": useful_flops(n, n, 20, with_p=False) / (ms * 1e-3) / 1e12}
+    if checks is not None:
+        Yh = Y.cpu().numpy().astype(np.float64)
+
+        def check(oracle, pb=pb, Yh=Yh, dst=row):
+            # the constructed factors give [A]_r exactly (Eckart-Young)
+            ref = (pb.U[:, :r] * pb.sigma[:r]) @ pb.V[:, :r].T
+            dst["rel_err_vs_construction"] = float(np.linalg.norm(Yh - ref) / np.linalg.norm(ref))
+        checks.append(check)
+    return row
+
+
 def fig1_leg(psvt, torch, dev, checks, taus=(1.0, 17.0, 33.0), kmax=30):
     """Relative error against the number of polar iterations (the experiment
     of Fig. 1): one i.i.d. Gaussian 301 x 300 matrix (singular values inside
@@ -409,8 +433,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
-    ap.add_argument("--forms", default="small,precision,batched,serving,fig1,fig2",
-                    help="comma-separated subset of the small / precision / batched / serving / fig1 / fig2 legs")
+    ap.add_argument("--forms", default="small,rank,precision,batched,serving,fig1,fig2",
+                    help="comma-separated subset of the small / rank / precision / batched / serving / fig1 / fig2 "
+                         "legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
@@ -521,6 +546,10 @@ def main():
         if "small" in want:
             print("[bench] small case latency ...", file=sys.stderr, flush=True)
             forms["small_256x128"] = small_leg(psvt, torch, dev, checks)
+        if "rank" in want:
+            print("[bench] rank-r approximation (Corollary 1) ...", file=sys.stderr, flush=True)
+            forms["rank_r_4096_r256"] = rank_leg(psvt, torch, dev, checks)
+            torch.cuda.empty_cache()
         if "precision" in want:
             print("[bench] precision form ...", file=sys.stderr, flush=True)
             forms["precision"] = precision_leg(psvt, torch, dev, checks, problems)
