@@ -174,7 +174,7 @@ def precision_leg(psvt, torch, dev, checks, problems=None):
             row[name] = {"ms": ms, "matrices_per_s": 1e3 / ms,
                          "useful_tflops": useful_flops(m, n, 20) / (ms * 1e-3) / 1e12,
                          "mfma_util_by_dtype": {d: (f / (t * 1e-3) / 1e12) / peak[d] for d, (f, t) in mfma.items()}}
-            if checks is not None and m > n:
+            if checks is not None:
                 Yh = Y.cpu().numpy().astype(np.float64)
 
                 def check(oracle, pb=pb, Yh=Yh, dst=row[name]):
@@ -377,7 +377,7 @@ def fig2_leg(psvt, torch, dev, checks, sizes=(1000, 2000, 3000, 4000, 5000), dra
     return out
 
 
-def serving_leg(psvt, torch, dev, rates=(200, 1000, 5000), count=300):
+def serving_leg(psvt, torch, dev, rates=(100, 200, 1000, 5000), count=300):
     """Serving form: Poisson arrivals, sizes 256..4096 square and 2:1, rank
     r in {16, 64, 256} + noise, 6 FP8 + 12 BF16 + 2 FP32 iterations."""
     from paper_2607_22484_amd import inputs
