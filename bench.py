@@ -392,8 +392,8 @@ def serving_leg(psvt, torch, dev, rates=(100, 200, 1000, 5000), count=300):
         reqs.append((A, 2 * 0.01 * (math.sqrt(m) + math.sqrt(n)) / math.sqrt(n)))
     torch.cuda.synchronize()
     out = {}
-    # the plain FP32 form on the first 100 requests, one matrix per launch sequence
-    sample = reqs[:100]
+    # the plain FP32 form on the same requests, one matrix per launch sequence
+    sample = reqs
     cfg, _ = psvt.make_config(iters=20)
     ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, A.shape[0], A.shape[1], cfg) for A, _ in sample),
                      dtype=torch.uint8, device=dev)
@@ -404,6 +404,18 @@ def serving_leg(psvt, torch, dev, rates=(100, 200, 1000, 5000), count=300):
             psvt.svt(A, tau, iters=20, out=Y, ws=ws)
     ms = time_calls(torch, single, 1)
     out["fp32_single_calls"] = {"requests": len(sample), "matrices_per_s": len(sample) / (ms * 1e-3)}
+    del ws
+    # the served schedule as single calls, one request at a time (no batching)
+    lp = dict(n_fp8=6, n_bf16=12)
+    cfg, _ = psvt.make_config(iters=20, **lp)
+    ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, A.shape[0], A.shape[1], cfg) for A, _ in sample),
+                     dtype=torch.uint8, device=dev)
+
+    def single_lp():
+        for (A, tau), Y in zip(sample, Ys):
+            psvt.svt(A, tau, iters=20, out=Y, ws=ws, **lp)
+    ms = time_calls(torch, single_lp, 1)
+    out["lp_single_calls"] = {"requests": len(sample), "matrices_per_s": len(sample) / (ms * 1e-3)}
     del ws, Ys
     for rate in rates:
         srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, iters=20, n_fp8=6, n_bf16=12)
