@@ -168,8 +168,10 @@ int psvt_batch_destroy(psvt_batch *batch);
  * iterates stay in its workspace on the device until it completes.
  * Admitted requests are split by size (s^2 l, s and l the short and long
  * side) into four lanes.  The worker runs ticks per lane: every active
- * request of the lane advances by up to 3 stages of its stage list; a
- * round's stages are grouped by kind (products also by operand type and tile
+ * request of the lane advances by up to 3 stages of its stage list (for a
+ * short side <= 2048 by up to 3 stages of each of its P and S iteration
+ * chains, which then have separate buffers, as in psvt_svt); a round's
+ * stages are grouped by kind (products also by operand type and tile
  * configuration) into grouped launches, so requests at different points of
  * their iteration share launches and newcomers join at the next tick
  * (iteration-level continuous batching).  Each lane has its own stream, so

@@ -753,8 +753,14 @@ int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, dou
     Exec exP;
     exP.st = side ? side->st : ex.st;
     exP.rec = ex.rec;
+    if (ex.rec) {
+        ex.cut[0] = ex.rec->size();
+        ex.chains = L.fork;
+    }
     if (op == PSVT_OP_SVT) rc = polar_iterations(c, L, ws, exP, nullptr, 0, &P);
+    if (ex.rec) ex.cut[1] = ex.rec->size();
     if (!rc) rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi);
+    if (ex.rec) ex.cut[2] = ex.rec->size();
     if (side) {
         // joined on failure too: after an error the caller may free ws as
         // soon as its own stream is done, so no side-stream work may remain
@@ -792,25 +798,31 @@ namespace psvt {
 
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 
-// Stage list of one batch item (records, launches nothing).  ws == NULL:
-// only report the workspace size.
+// Stage list of one batch item or served request (records, launches
+// nothing).  ws == NULL: only report the workspace size.  chains != NULL (a
+// served request): the layout of a single call, whose P and S iterations may
+// run concurrently for short sides <= 2048, and chains[0..2] = the plan's
+// chain boundaries (the whole plan as one prefix when they may not).
 int plan_request(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, std::vector<Stage> &out,
-                 size_t *ws_bytes, bool check_dev) {
+                 size_t *ws_bytes, bool check_dev, size_t *chains) {
     Cfg c;
     int rc = read_cfg(cfg, c);
     if (rc) return rc;
-    Layout L = make_layout(op, it.m, it.n, c);
+    Layout L = make_layout(op, it.m, it.n, c, chains != nullptr);
     *ws_bytes = L.total;
     if (!ws) return PSVT_OK;
     if (check_dev && (rc = check_device())) return rc;
     Exec ex;
     ex.rec = &out;
-    return plan_svt_like(op, it.A, it.m, it.n, it.lda, it.tau, it.Y, it.ldy, ws, L, c, ex);
+    if ((rc = plan_svt_like(op, it.A, it.m, it.n, it.lda, it.tau, it.Y, it.ldy, ws, L, c, ex))) return rc;
+    if (chains)
+        for (int i = 0; i < 3; ++i) chains[i] = ex.chains ? ex.cut[i] : out.size();
+    return PSVT_OK;
 }
 
 int batch_plan_one(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, std::vector<Stage> &out,
                    size_t *ws_bytes) {
-    return plan_request(op, it, ws, cfg, out, ws_bytes, true);
+    return plan_request(op, it, ws, cfg, out, ws_bytes, true, nullptr);
 }
 
 }  // namespace psvt

@@ -24,6 +24,13 @@ struct Stage {
 struct Exec {
     hipStream_t st = nullptr;
     std::vector<Stage> *rec = nullptr;  // record instead of launching
+    // A recorded soft-thresholding: stages [0, cut[0]) are the common prefix
+    // (norm, Gram, shifted Gram), [cut[0], cut[1]) the P iterations,
+    // [cut[1], cut[2]) the S iterations, the rest the final product.  With
+    // `chains` set the two iteration chains touch disjoint buffers and may
+    // run concurrently.
+    size_t cut[3] = {0, 0, 0};
+    bool chains = false;
 
     hipError_t gemm(const GemmArgs &g, int dt, const char *what) {
         if (g.M <= 0 || g.N <= 0) return hipSuccess;

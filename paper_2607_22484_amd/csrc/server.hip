@@ -41,7 +41,7 @@ using namespace psvt;
 
 namespace psvt {
 int plan_request(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, std::vector<Stage> &out,
-                 size_t *ws_bytes, bool check_dev);
+                 size_t *ws_bytes, bool check_dev, size_t *chains);
 int set_error(int code, const char *msg);
 }  // namespace psvt
 
@@ -106,12 +106,48 @@ struct Request {
     psvt_batch_item item;
     size_t ws_bytes = 0, ws_off = 0;
     std::vector<Stage> plan;
-    size_t cursor = 0;
+    // plan[0, cut[0]) common prefix, [cut[0], cut[1]) P iterations, [cut[1],
+    // cut[2]) S iterations, then the final product; the two iteration chains
+    // advance independently (a round takes the next stage of each)
+    size_t cut[3] = {0, 0, 0};
+    size_t cursor = 0, curP = 0, curS = 0;
     int state = RQ_QUEUED;
     int64_t finish_tick = -1;  // lane tick that launched the last stage
     int lane = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
 };
+
+// Stages a request can run next (at most two: one of each iteration chain).
+int next_stages(const Request *r, size_t idx[2]) {
+    if (r->cursor < r->cut[0]) {
+        idx[0] = r->cursor;
+        return 1;
+    }
+    int n = 0;
+    if (r->curP < r->cut[1]) idx[n++] = r->curP;
+    if (r->curS < r->cut[2]) idx[n++] = r->curS;
+    if (n) return n;
+    const size_t f = std::max(r->cursor, r->cut[2]);
+    if (f < r->plan.size()) {
+        idx[0] = f;
+        return 1;
+    }
+    return 0;
+}
+
+bool plan_done(const Request *r) {
+    size_t idx[2];
+    return next_stages(r, idx) == 0;
+}
+
+void advance(Request *r, size_t i) {
+    if (i < r->cut[0] || i >= r->cut[2])
+        r->cursor = i + 1;
+    else if (i < r->cut[1])
+        r->curP = i + 1;
+    else
+        r->curS = i + 1;
+}
 
 // Lane of a request: by s^2 l (s, l the short and long side), the scale of
 // its flops, in factors of 8 from 512^3.
@@ -192,13 +228,20 @@ struct Group {
 // seg_used), the requests' cursors advanced; the launches are appended to gl.
 int build_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *> &reqs, int seg, size_t &seg_used,
                 std::vector<Group> &gl) {
-    std::map<GroupKey, std::vector<Request *>> groups;
+    typedef std::pair<Request *, size_t> Entry;  // (request, stage index)
+    std::map<GroupKey, std::vector<Entry>> groups;
+    std::vector<Entry> taken;
     for (Request *r : reqs) {
-        const Stage &st = r->plan[r->cursor];
-        GroupKey k{st.kind, st.kind == ST_GEMM ? st.dtype : 0, st.kind == ST_GEMM ? st.g.sym : 0,
-                   st.kind == ST_GEMM ? (st.g.A2 != nullptr) : 0, st.kind == ST_GEMM ? gemm_pick_tile(st.g, st.dtype) : 0,
-                   st.kind == ST_TILE ? st.t.kind : 0};
-        groups[k].push_back(r);
+        size_t idx[2];
+        const int n = next_stages(r, idx);
+        for (int e = 0; e < n; ++e) {
+            const Stage &st = r->plan[idx[e]];
+            GroupKey k{st.kind, st.kind == ST_GEMM ? st.dtype : 0, st.kind == ST_GEMM ? st.g.sym : 0,
+                       st.kind == ST_GEMM ? (st.g.A2 != nullptr) : 0,
+                       st.kind == ST_GEMM ? gemm_pick_tile(st.g, st.dtype) : 0, st.kind == ST_TILE ? st.t.kind : 0};
+            groups[k].push_back(Entry(r, idx[e]));
+            taken.push_back(Entry(r, idx[e]));
+        }
     }
     char *hseg = lane.ring_host + (size_t)seg * psvt_server::kSegBytes;
     const size_t first = gl.size();
@@ -207,9 +250,9 @@ int build_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *> 
         const GroupKey &k = kv.first;
         auto &rs = kv.second;
         if (k.kind == ST_GEMM)  // largest first
-            std::stable_sort(rs.begin(), rs.end(), [&](Request *a, Request *b) {
-                return gemm_model_us(a->plan[a->cursor].g, k.dtype, k.tile) >
-                       gemm_model_us(b->plan[b->cursor].g, k.dtype, k.tile);
+            std::stable_sort(rs.begin(), rs.end(), [&](const Entry &a, const Entry &b) {
+                return gemm_model_us(a.first->plan[a.second].g, k.dtype, k.tile) >
+                       gemm_model_us(b.first->plan[b.second].g, k.dtype, k.tile);
             });
         const size_t esz = k.kind == ST_GEMM ? sizeof(GemmArgs) : (k.kind == ST_NORM ? sizeof(NormOp) : sizeof(TileOp));
         const size_t need = align256(esz * rs.size()) + align256(sizeof(int) * rs.size());
@@ -217,7 +260,7 @@ int build_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *> 
         char *hops = hseg + seg_used, *hpre = hops + align256(esz * rs.size());
         Group G{k, seg_used, (int)rs.size(), 0, 0.0, 0.0};
         for (size_t i = 0; i < rs.size(); ++i) {
-            const Stage &st = rs[i]->plan[rs[i]->cursor];
+            const Stage &st = rs[i].first->plan[rs[i].second];
             ((int *)hpre)[i] = G.total;
             if (k.kind == ST_GEMM) {
                 ((GemmArgs *)hops)[i] = st.g;
@@ -237,7 +280,7 @@ int build_round(psvt_server *s, psvt_server::Lane &lane, std::vector<Request *> 
         gl.push_back(G);
     }
     s->launches += (int64_t)(gl.size() - first);
-    for (Request *r : reqs) r->cursor++;
+    for (const Entry &e : taken) advance(e.first, e.second);
     return PSVT_OK;
 }
 
@@ -294,7 +337,10 @@ void worker_main(psvt_server *s) {
             r->ws_off = off;
             r->plan.clear();
             const int rc = plan_request(r->op, r->item, s->fake ? (void *)(uintptr_t)(4096 + off) : s->pool_dev + off,
-                                        &s->cfg, r->plan, &r->ws_bytes, !s->fake);
+                                        &s->cfg, r->plan, &r->ws_bytes, !s->fake, r->cut);
+            r->cursor = 0;
+            r->curP = r->cut[0];
+            r->curS = r->cut[1];
             s->queue.pop_front();
             r->t_admit = now_s();
             if (rc != PSVT_OK) {
@@ -339,7 +385,7 @@ void worker_main(psvt_server *s) {
             psvt_server::Lane &ln = s->lanes[li];
             std::vector<Request *> runnable;
             for (Request *r : s->active)
-                if (r->lane == li && r->cursor < r->plan.size()) runnable.push_back(r);
+                if (r->lane == li && !plan_done(r)) runnable.push_back(r);
             if (runnable.empty()) continue;
             any_runnable = true;
             // reuse the lane's oldest segment only once its tick has finished
@@ -351,7 +397,7 @@ void worker_main(psvt_server *s) {
             for (int round = 0; round < s->rounds && rc == PSVT_OK; ++round) {
                 std::vector<Request *> rr;
                 for (Request *r : runnable)
-                    if (r->cursor < r->plan.size()) rr.push_back(r);
+                    if (!plan_done(r)) rr.push_back(r);
                 if (rr.empty()) break;
                 rc = build_round(s, ln, rr, seg, seg_used, gl);
             }
@@ -361,7 +407,7 @@ void worker_main(psvt_server *s) {
                 ln.seg_tick[seg] = ln.tick;
             }
             for (Request *r : runnable)
-                if (r->cursor >= r->plan.size() && r->finish_tick < 0) r->finish_tick = ln.tick;
+                if (plan_done(r) && r->finish_tick < 0) r->finish_tick = ln.tick;
             s->ticks++;
             ++ln.tick;
             launched = true;
@@ -464,7 +510,8 @@ int psvt_server_submit(psvt_server *s, int op, const psvt_batch_item *item, uint
     r->op = op;
     r->item = it;
     std::vector<Stage> none;
-    int rc = plan_request(op, it, nullptr, &s->cfg, none, &r->ws_bytes, false);
+    size_t cut[3];
+    int rc = plan_request(op, it, nullptr, &s->cfg, none, &r->ws_bytes, false, cut);
     if (rc != PSVT_OK) {
         delete r;
         return rc;
