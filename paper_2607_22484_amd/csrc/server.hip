@@ -112,6 +112,7 @@ struct Request {
     size_t cut[3] = {0, 0, 0};
     size_t cursor = 0, curP = 0, curS = 0;
     int state = RQ_QUEUED;
+    bool parked = false;       // admitted, waiting for the lane's next cohort
     int64_t finish_tick = -1;  // lane tick that launched the last stage
     int lane = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -163,6 +164,7 @@ int lane_of(const psvt_batch_item &it, int nlanes) {
 
 struct psvt_server {
     bool fake = false;
+    bool cohort = false;  // lanes start admitted requests in cohorts
     size_t budget = 0;
     int max_slots = 1, rounds = 3, depth = 3;
     psvt_config cfg{};
@@ -350,6 +352,12 @@ void worker_main(psvt_server *s) {
             }
             r->state = RQ_RUNNING;
             r->lane = lane_of(r->item, psvt_server::kLanes);
+            if (s->cohort)  // a lane's running cohort is not joined half-way
+                for (Request *o : s->active)
+                    if (o->lane == r->lane && !o->parked && o->cursor > 0 && !plan_done(o)) {
+                        r->parked = true;
+                        break;
+                    }
             s->active.push_back(r);
         }
         // completions
@@ -385,7 +393,14 @@ void worker_main(psvt_server *s) {
             psvt_server::Lane &ln = s->lanes[li];
             std::vector<Request *> runnable;
             for (Request *r : s->active)
-                if (r->lane == li && !plan_done(r)) runnable.push_back(r);
+                if (r->lane == li && !r->parked && !plan_done(r)) runnable.push_back(r);
+            if (runnable.empty()) {  // the lane's cohort is through: the parked requests start together
+                for (Request *r : s->active)
+                    if (r->lane == li && r->parked) {
+                        r->parked = false;
+                        runnable.push_back(r);
+                    }
+            }
             if (runnable.empty()) continue;
             any_runnable = true;
             // reuse the lane's oldest segment only once its tick has finished
@@ -449,9 +464,10 @@ int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config
     *out = nullptr;
     if (budget_bytes < 4096 || max_slots < 1 || max_slots > 4096)
         return set_error(PSVT_EINVAL, "bad budget or slot count");
-    if (flags & ~(uint32_t)PSVT_SERVER_FAKE) return set_error(PSVT_EINVAL, "unknown server flags");
+    if (flags & ~(uint32_t)(PSVT_SERVER_FAKE | PSVT_SERVER_COHORT)) return set_error(PSVT_EINVAL, "unknown server flags");
     psvt_server *s = new psvt_server();
     s->fake = (flags & PSVT_SERVER_FAKE) != 0;
+    s->cohort = (flags & PSVT_SERVER_COHORT) != 0;
     s->budget = budget_bytes;
     s->max_slots = max_slots;
     if (cfg) {

@@ -32,12 +32,13 @@ def _requests(count, idx):
             enumerate(shapes)]
 
 
-def test_mix_equals_alone_and_oracle(gpu_lib, tdev):
+@pytest.mark.parametrize("cohort", [False, True])
+def test_mix_equals_alone_and_oracle(gpu_lib, tdev, cohort):
     torch, dev = tdev
     pbs = _requests(10, idx=1)
-    _announce("serve mix %s" % [p.shape for p in pbs])
+    _announce("serve mix cohort=%s %s" % (cohort, [p.shape for p in pbs]))
     As = [torch.from_numpy(p.A).to(dev) for p in pbs]
-    srv = gpu_lib.Server(budget_bytes=1 << 30, max_slots=16, **SCHED)
+    srv = gpu_lib.Server(budget_bytes=1 << 30, max_slots=16, cohort=cohort, **SCHED)
     tickets = []
     for A, p in zip(As, pbs):
         tickets.append(srv.submit(A, p.tau))

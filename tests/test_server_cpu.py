@@ -118,3 +118,25 @@ def test_threads_submitting_concurrently():
     assert len(set(out)) == 100
     assert srv.stats()["completed"] == 100
     srv.close()
+
+
+def test_cohort_admission_completes_everything():
+    """PSVT_SERVER_COHORT: requests admitted while their lane runs a started
+    cohort wait for it and then start together; everything completes, in
+    every lane, and bad flags are rejected."""
+    srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, fake=True, cohort=True)
+    shapes = [(4096, 2048), (2048, 2048), (1024, 1024), (512, 512), (64, 64)] * 4
+    tickets = []
+    for i, (m, n) in enumerate(shapes):
+        tickets.append(submit(srv, m, n))
+        if i % 5 == 4:
+            time.sleep(0.002)  # later arrivals meet running cohorts
+    srv.drain(timeout=60)
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in tickets)
+    st = srv.stats()
+    assert st["completed"] == len(shapes) and st["failed"] == 0 and st["active"] == 0
+    srv.close()
+    lib = psvt.load()
+    import ctypes
+    h = ctypes.c_void_p()
+    assert lib.psvt_server_create(1 << 20, 4, None, 0x4, ctypes.byref(h)) == psvt.PSVT_EINVAL
