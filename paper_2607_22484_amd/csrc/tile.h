@@ -575,7 +575,9 @@ __global__ __launch_bounds__(256, OCC) void gemm_grouped(const GemmArgs *args, c
         else
             hi = mid - 1;
     }
-    const GemmArgs &g = args[lo];
+    // a copy: the fields then live in registers for the whole tile instead
+    // of being re-read from the descriptor table after every store
+    const GemmArgs g = args[lo];
     int bi, bj;
     tile_coords<SYM>(b - prefix[lo], g.M, g.N, BM, BN, bi, bj);
     if constexpr (!TWO_A) {
