@@ -191,11 +191,13 @@ __global__ __launch_bounds__(256) void fro_final(NormOp op) {
 __global__ __launch_bounds__(256) void fro_partial_grouped(const NormOp *ops, const int *prefix, int n) {
     __shared__ double red[256];
     const int p = find_group(prefix, n, blockIdx.x);
-    fro_partial_body(ops[p], blockIdx.x - prefix[p], red);
+    const NormOp op = ops[p];  // in registers, not re-read from the table after stores
+    fro_partial_body(op, blockIdx.x - prefix[p], red);
 }
 __global__ __launch_bounds__(256) void fro_final_grouped(const NormOp *ops) {
     __shared__ double red[256];
-    fro_final_body(ops[blockIdx.x], red);
+    const NormOp op = ops[blockIdx.x];
+    fro_final_body(op, red);
 }
 
 NormOp make_norm_op(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials, Scalars *sc, int mode,
@@ -304,7 +306,8 @@ __global__ __launch_bounds__(256) void tile_op(TileOp op) {
 __global__ __launch_bounds__(256) void tile_op_grouped(const TileOp *ops, const int *prefix, int n) {
     __shared__ float lds[64][65];
     const int p = find_group(prefix, n, blockIdx.x);
-    tile_op_body(ops[p], blockIdx.x - prefix[p], lds);
+    const TileOp op = ops[p];  // in registers, not re-read from the table after stores
+    tile_op_body(op, blockIdx.x - prefix[p], lds);
 }
 
 int tile_op_tiles(const TileOp &op) { return (int)(((op.rows + 63) / 64) * ((op.cols + 63) / 64)); }
