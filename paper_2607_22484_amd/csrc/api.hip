@@ -739,6 +739,13 @@ SideStream *side_stream() {
     return &s;
 }
 
+// One recorded stage, launched on `st`.
+hipError_t launch_stage(const Stage &s, hipStream_t st) {
+    if (s.kind == ST_GEMM) return launch_gemm(s.g, s.dtype, st);
+    if (s.kind == ST_NORM) return launch_norm_op(s.n, st);
+    return launch_tile_op(s.t, st);
+}
+
 int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
                   void *ws, const Layout &L, const Cfg &c, Exec &ex) {
     int rc;
@@ -750,17 +757,32 @@ int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, dou
         HIP_TRY(hipEventRecord(side->fork, ex.st), "fork");
         HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0), "fork");
     }
-    Exec exP;
-    exP.st = side ? side->st : ex.st;
-    exP.rec = ex.rec;
-    if (ex.rec) {
-        ex.cut[0] = ex.rec->size();
-        ex.chains = L.fork;
+    if (side) {
+        // both chains recorded first, then enqueued alternately, so that the
+        // S stream has work from the start instead of after all of P's
+        // launches (the host's launch rate bounds the small sizes)
+        std::vector<Stage> sp, ss;
+        Exec rp, rs;
+        rp.rec = &sp;
+        rs.rec = &ss;
+        rc = polar_iterations(c, L, ws, rp, nullptr, 0, &P);
+        if (!rc) rc = sign_iterations(c, L, ws, rs, true, nullptr, 0, &Pi);
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; !rc && e == hipSuccess && (i < sp.size() || i < ss.size()); ++i) {
+            if (i < sp.size()) e = launch_stage(sp[i], side->st);
+            if (e == hipSuccess && i < ss.size()) e = launch_stage(ss[i], ex.st);
+        }
+        if (!rc && e != hipSuccess) rc = hip_fail(e, "iterations");
+    } else {
+        if (ex.rec) {
+            ex.cut[0] = ex.rec->size();
+            ex.chains = L.fork;
+        }
+        if (op == PSVT_OP_SVT) rc = polar_iterations(c, L, ws, ex, nullptr, 0, &P);
+        if (ex.rec) ex.cut[1] = ex.rec->size();
+        if (!rc) rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi);
+        if (ex.rec) ex.cut[2] = ex.rec->size();
     }
-    if (op == PSVT_OP_SVT) rc = polar_iterations(c, L, ws, exP, nullptr, 0, &P);
-    if (ex.rec) ex.cut[1] = ex.rec->size();
-    if (!rc) rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi);
-    if (ex.rec) ex.cut[2] = ex.rec->size();
     if (side) {
         // joined on failure too: after an error the caller may free ws as
         // soon as its own stream is done, so no side-stream work may remain
