@@ -417,7 +417,9 @@ def serving_leg(psvt, torch, dev, rates=(100, 200, 1000, 5000), count=300):
     ms = time_calls(torch, single_lp, 1)
     out["lp_single_calls"] = {"requests": len(sample), "matrices_per_s": len(sample) / (ms * 1e-3)}
     del ws, Ys
-    runs = [(rate, False) for rate in rates] + [(rate, True) for rate in rates if rate in (200, 5000)]
+    # cohort admission (the server's default), and at two rates the eager
+    # joining it replaces
+    runs = [(rate, True) for rate in rates] + [(rate, False) for rate in rates if rate in (200, 5000)]
     for rate, cohort in runs:
         srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, iters=20, n_fp8=6, n_bf16=12, cohort=cohort)
         gaps = np.random.default_rng(rate).exponential(1.0 / rate, size=len(reqs))
@@ -429,7 +431,7 @@ def serving_leg(psvt, torch, dev, rates=(100, 200, 1000, 5000), count=300):
             srv.submit(A, tau)
         srv.drain(timeout=600)
         st = srv.stats()
-        out["%d_per_s%s" % (rate, "_cohort" if cohort else "")] = {
+        out["%d_per_s%s" % (rate, "" if cohort else "_eager")] = {
             "completed": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "launches": st["launches"],
             "matrices_per_s": st["matrices_per_s"], "queue_p99_ms": st["queue_p99_ms"],
             "peak_pool_gib": st["peak_bytes"] / 2 ** 30}

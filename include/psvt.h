@@ -180,11 +180,14 @@ int psvt_batch_destroy(psvt_batch *batch);
  * server's psvt_config (its coeffs are copied).
  *   create:  allocates the pool, the lanes' streams and descriptor rings;
  *            PSVT_SERVER_FAKE runs the scheduler without a device (stages
- *            complete at once; for tests).  PSVT_SERVER_COHORT: a request
- *            admitted while its lane runs requests that have started waits
- *            until they have launched their last stage, then starts with the
- *            other waiting ones, so a cohort's requests sit at the same stage
- *            and share launches (more throughput, more latency).
+ *            complete at once; for tests).  Cohort admission (the default;
+ *            PSVT_SERVER_COHORT asks for it explicitly): a request admitted
+ *            while its lane runs requests that have started waits until they
+ *            have launched their last stage, then starts with the other
+ *            waiting ones, so a cohort's requests sit at the same stage and
+ *            share launches.  PSVT_SERVER_EAGER: a request joins its lane's
+ *            running requests at once instead (they then rarely share a
+ *            stage).  Setting both is PSVT_EINVAL.
  *   submit:  non-blocking; A is read and Y written by the device at some
  *            later time, so both must stay valid until the request is done.
  *            PSVT_EWORKSPACE if the request could never fit the budget.
@@ -193,6 +196,7 @@ int psvt_batch_destroy(psvt_batch *batch);
  *   stats:   latency = completion observed by the worker - submit time. */
 #define PSVT_SERVER_FAKE 0x1u
 #define PSVT_SERVER_COHORT 0x2u
+#define PSVT_SERVER_EAGER 0x4u
 typedef struct psvt_server psvt_server;
 typedef struct psvt_server_counters {
     int64_t submitted, completed, failed, queued, active, ticks, launches;

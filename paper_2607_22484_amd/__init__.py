@@ -36,7 +36,7 @@ EXPORTED = [
     "psvt_batch_destroy", "psvt_server_create", "psvt_server_submit", "psvt_server_poll", "psvt_server_wait",
     "psvt_server_drain", "psvt_server_stats", "psvt_server_destroy",
 ]
-SERVER_FAKE, SERVER_COHORT = 0x1, 0x2
+SERVER_FAKE, SERVER_COHORT, SERVER_EAGER = 0x1, 0x2, 0x4
 RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_FAILED = 0, 1, 2, -1
 TILE_IDS = {64: 1, 128: 2, 192: 3, 256: 4}
 TUNE_TABLE = os.path.join(_HERE, "tune_table.txt")
@@ -425,10 +425,10 @@ class Server:
     iteration-level continuous batching, latency statistics."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 64, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0,
-                 flags: int = 0, fake: bool = False, side: int = SIDE_AUTO, cohort: bool = False):
+                 flags: int = 0, fake: bool = False, side: int = SIDE_AUTO, cohort: bool = True):
         self.cfg, self._keep = make_config(iters, n_fp8, n_bf16, side, None, flags)
         h = ctypes.c_void_p()
-        sflags = (SERVER_FAKE if fake else 0) | (SERVER_COHORT if cohort else 0)
+        sflags = (SERVER_FAKE if fake else 0) | (0 if cohort else SERVER_EAGER)
         _check(load().psvt_server_create(int(budget_bytes), int(max_slots), ctypes.byref(self.cfg),
                                          sflags, ctypes.byref(h)), "psvt_server_create")
         self._h = h

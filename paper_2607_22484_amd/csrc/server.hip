@@ -464,10 +464,13 @@ int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config
     *out = nullptr;
     if (budget_bytes < 4096 || max_slots < 1 || max_slots > 4096)
         return set_error(PSVT_EINVAL, "bad budget or slot count");
-    if (flags & ~(uint32_t)(PSVT_SERVER_FAKE | PSVT_SERVER_COHORT)) return set_error(PSVT_EINVAL, "unknown server flags");
+    if (flags & ~(uint32_t)(PSVT_SERVER_FAKE | PSVT_SERVER_COHORT | PSVT_SERVER_EAGER))
+        return set_error(PSVT_EINVAL, "unknown server flags");
+    if ((flags & PSVT_SERVER_COHORT) && (flags & PSVT_SERVER_EAGER))
+        return set_error(PSVT_EINVAL, "PSVT_SERVER_COHORT and PSVT_SERVER_EAGER exclude each other");
     psvt_server *s = new psvt_server();
     s->fake = (flags & PSVT_SERVER_FAKE) != 0;
-    s->cohort = (flags & PSVT_SERVER_COHORT) != 0;
+    s->cohort = (flags & PSVT_SERVER_EAGER) == 0;
     s->budget = budget_bytes;
     s->max_slots = max_slots;
     if (cfg) {

@@ -121,9 +121,9 @@ def test_threads_submitting_concurrently():
 
 
 def test_cohort_admission_completes_everything():
-    """PSVT_SERVER_COHORT: requests admitted while their lane runs a started
-    cohort wait for it and then start together; everything completes, in
-    every lane, and bad flags are rejected."""
+    """Cohort admission (the default): requests admitted while their lane
+    runs a started cohort wait for it and then start together; everything
+    completes, in every lane, and bad flag sets are rejected."""
     srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, fake=True, cohort=True)
     shapes = [(4096, 2048), (2048, 2048), (1024, 1024), (512, 512), (64, 64)] * 4
     tickets = []
@@ -139,4 +139,15 @@ def test_cohort_admission_completes_everything():
     lib = psvt.load()
     import ctypes
     h = ctypes.c_void_p()
-    assert lib.psvt_server_create(1 << 20, 4, None, 0x4, ctypes.byref(h)) == psvt.PSVT_EINVAL
+    assert lib.psvt_server_create(1 << 20, 4, None, 0x8, ctypes.byref(h)) == psvt.PSVT_EINVAL
+    assert lib.psvt_server_create(1 << 20, 4, None, psvt.SERVER_COHORT | psvt.SERVER_EAGER,
+                                  ctypes.byref(h)) == psvt.PSVT_EINVAL
+
+
+def test_eager_admission_completes_everything():
+    srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, fake=True, cohort=False)
+    shapes = [(2048, 1024), (512, 512), (64, 64)] * 4
+    tickets = [submit(srv, m, n) for m, n in shapes]
+    srv.drain(timeout=60)
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in tickets)
+    srv.close()
