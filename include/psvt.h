@@ -172,9 +172,11 @@ int psvt_batch_destroy(psvt_batch *batch);
  * short side <= 2048 by up to 3 stages of each of its P and S iteration
  * chains, which then have separate buffers, as in psvt_svt); a round's
  * stages are grouped by kind (products also by operand type and tile
- * configuration) into grouped launches, so requests at different points of
- * their iteration share launches and newcomers join at the next tick
- * (iteration-level continuous batching).  Each lane has its own stream, so
+ * configuration) into grouped launches, so requests at the same stage share
+ * launches.  Newcomers start with the lane's next cohort (below), or at the
+ * next tick with PSVT_SERVER_EAGER; either way requests enter and leave a
+ * running lane without draining the server (continuous batching).  Each
+ * lane has its own stream, so
  * lanes overlap on the device.  Tiles are computed exactly as in single
  * calls, so a result is the same alone and in the mix.  All requests use the
  * server's psvt_config (its coeffs are copied).
