@@ -23,8 +23,11 @@ by the one-sided Jacobi routine in ``jacobi.c`` (FP64):
 * ``svt_from_svd``     -- Eq. (1) for factors already known (constructed
                           spectra): no SVD is computed.
 * ``svt_gapped``       -- Eq. (1) for large low-rank-plus-noise inputs, by the
-                          Jacobi SVD of a compressed matrix whose range holds
-                          every singular vector above tau (checked).
+                          Jacobi SVD of a compressed matrix, accepted only
+                          under a certified bound on its error.
+* ``prox_error_bound`` -- a rigorous upper bound on ||Y - A_tau||_F for any
+                          candidate Y, from the duality gap of the prox
+                          problem whose solution A_tau is (section 2).
 
 Inputs are widened to float64 before anything else; callers hand in exactly
 the FP32 matrix the GPU sees.
@@ -32,6 +35,7 @@ the FP32 matrix the GPU sees.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -139,37 +143,118 @@ def rank_r(A, tau, nthreads: int = 0):
     return (U * keep) @ V.T
 
 
-def svt_gapped(A, tau, k, power_iters=6, seed=0, nthreads: int = 0):
+def prox_error_bound(A, Y, tau, factor=None):
+    """Certified upper bound on ||Y - A_tau||_F for any candidate Y.
+
+    A_tau is the proximal point of tau ||.||_* at A (section 2: the
+    subroutine of nuclear-norm proximal methods), i.e. the minimiser of the
+    1-strongly convex f(X) = ||X - A||_F^2 / 2 + tau ||X||_*, so
+    ||Y - A_tau||_F^2 / 2 <= f(Y) - d(Z) for every dual-feasible Z.  The dual
+    is d(Z) = <A, Z> - ||Z||_F^2 / 2 over ||Z||_2 <= tau (the spectral norm
+    is the dual of the nuclear norm).  With M = A - Y and Z = c M,
+    0 <= c <= 1, c ||M||_2 <= tau:
+
+        f(Y) - d(cM) = tau ||Y||_* - c <Y, M> + (1 - c)^2 ||M||_F^2 / 2.
+
+    Any upper bound on ||Y||_* and on ||M||_2 keeps the result an upper
+    bound.  ||Y||_*: the singular values of Y (LAPACK), or, for
+    factor = (Q, Z) with Y = Q Z and Q (nearly) orthonormal,
+    sqrt(1 + ||Q^T Q - I||_2) ||Z||_*.  ||M||_2: the block form of M^T M in
+    an orthonormal basis [W, W_perp], W = the right singular vectors of Y's
+    nonzero part:
+
+        lambda_max(M^T M) <= lambda_max([[alpha, beta], [beta, gamma]]),
+        alpha = lambda_max(W^T M^T M W)          (small eigenproblem)
+        beta  = ||W^T M^T M W_perp||_2            (small SVD)
+        gamma = lambda_max(W_perp^T M^T M W_perp) <= ||C^8||_F^(1/8),
+                C = (M W_perp)^T (M W_perp)      (any power bounds it),
+
+    since x^T K x <= alpha |a|^2 + 2 beta |a||b| + gamma |b|^2 for
+    x = W a + W_perp b.  It is tight when W spans the top right singular
+    subspace of M (beta ~ 0, bound ~ alpha).  Returns (bound, parts)."""
+    A = np.asarray(A, np.float64)
+    Y = np.asarray(Y, np.float64)
+    m, n = A.shape
+    if m < n:
+        f = None if factor is None else (factor[1].T, factor[0].T)
+        if f is not None:
+            raise ValueError("pass the tall orientation with a factor")
+        return prox_error_bound(A.T, Y.T, tau)
+    M = A - Y
+    if factor is None:
+        _, sy, Vyt = np.linalg.svd(Y, full_matrices=False)
+        nuc = float(sy.sum())
+    else:
+        Q, Z = factor
+        e = float(np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1]), 2))
+        _, sy, Vyt = np.linalg.svd(np.asarray(Z, np.float64), full_matrices=False)
+        nuc = math.sqrt(1.0 + e) * float(sy.sum())
+    keep = sy > sy[0] * 1e-13 if sy.size and sy[0] > 0 else np.zeros(sy.shape, bool)
+    W = Vyt[keep].T
+    if W.shape[1]:
+        W, _ = np.linalg.qr(W)
+        MW = M @ W
+        alpha = float(np.linalg.eigvalsh(MW.T @ MW)[-1])
+        G = MW.T @ M
+        beta = float(np.linalg.norm(G - (G @ W) @ W.T, 2))
+        X = M - MW @ W.T
+    else:
+        alpha = beta = 0.0
+        X = M
+    C = X.T @ X if X.shape[0] >= X.shape[1] else X @ X.T
+    for _ in range(3):
+        C = C @ C
+    fro = float(np.linalg.norm(C))
+    gamma = (fro ** 0.125) * (1.0 + 1e-6) if fro > 0 else 0.0
+    lam = 0.5 * (alpha + gamma) + math.sqrt(0.25 * (alpha - gamma) ** 2 + beta * beta)
+    spec_up = math.sqrt(max(lam, 0.0)) * (1.0 + 1e-13)
+    c = 1.0 if spec_up <= tau else tau / spec_up
+    gap = tau * nuc - c * float(np.sum(Y * M)) + 0.5 * (1.0 - c) ** 2 * float(np.sum(M * M))
+    bound = math.sqrt(2.0 * max(gap, 0.0))
+    return bound, {"spec_upper": spec_up, "alpha": alpha, "beta": beta, "gamma_upper": gamma, "gap": gap,
+                   "nuclear": nuc}
+
+
+def svt_compressed(A, tau, Q, nthreads: int = 0):
+    """Eq. (1) through an orthonormal basis Q (m x k) of a subspace meant to
+    hold the left singular vectors of every sigma > tau:
+    Y = Q (Q^T A)_tau, with (Q^T A)_tau by the Jacobi SVD of the k x n
+    matrix.  Exact when that subspace is exactly invariant and the rest of A
+    has spectral norm <= tau; ``prox_error_bound`` certifies it."""
+    A = np.asarray(A, np.float64)
+    return Q @ svt(Q.T @ A, tau, nthreads)
+
+
+def svt_gapped(A, tau, k, power_iters=6, seed=0, nthreads: int = 0, max_rel_bound=1e-6, return_bound=False):
     """Eq. (1) for a large matrix whose singular values above tau are few and
     separated by a wide gap from the rest (low-rank signal plus noise, tau =
-    2 ||N||_2), computed on a compressed matrix:
+    2 ||N||_2), computed on a compressed matrix and then certified:
 
       Q = orthonormal basis of (A A^T)^q A Omega  (Omega: n x k Gaussian),
-      B = Q^T A (k x n),  A_tau = Q (B)_tau  with (B)_tau by the Jacobi SVD.
+      Y = Q (Q^T A)_tau,
 
-    Exact when range(Q) contains the left singular vectors of every
-    sigma > tau and the rest of A, (I - Q Q^T) A, has spectral norm <= tau;
-    the power steps make the first hold to working precision for a gapped
-    spectrum, and the second is checked (RuntimeError otherwise).  k must
-    exceed the number of singular values above tau."""
+    accepted only when the duality-gap bound of ``prox_error_bound`` gives
+    ||Y - A_tau||_F <= max_rel_bound ||Y||_F (RuntimeError otherwise).  The
+    bound holds for any Y, so acceptance does not rest on the randomised
+    basis being good.  k must exceed the number of singular values above
+    tau."""
     A = np.asarray(A, np.float64)
     m, n = A.shape
     if m < n:
-        return svt_gapped(A.T, tau, k, power_iters, seed, nthreads).T
+        out = svt_gapped(A.T, tau, k, power_iters, seed, nthreads, max_rel_bound, return_bound)
+        return (out[0].T, out[1]) if return_bound else out.T
     rng = np.random.default_rng(seed)
     Q, _ = np.linalg.qr(A @ rng.standard_normal((n, k)))
     for _ in range(power_iters):
         Q, _ = np.linalg.qr(A @ (A.T @ Q))
-    B = Q.T @ A
-    R = A - Q @ B
-    x = rng.standard_normal(n)
-    for _ in range(50):  # ||R||_2 by power iteration (an underestimate: pad 5%)
-        x = R.T @ (R @ x)
-        x /= np.linalg.norm(x)
-    rnorm = float(np.linalg.norm(R @ x))
-    if rnorm * 1.05 > tau:
-        raise RuntimeError("residual %.3g not below tau %.3g: increase k" % (rnorm, tau))
-    return Q @ svt(B, tau, nthreads)
+    Z = svt(Q.T @ A, tau, nthreads)
+    Y = Q @ Z
+    bound, _ = prox_error_bound(A, Y, tau, factor=(Q, Z))
+    ny = float(np.linalg.norm(Y))
+    rel = bound / ny if ny > 0 else bound
+    if not rel <= max_rel_bound:
+        raise RuntimeError("certified error bound %.3g exceeds %.3g: increase k or power_iters" % (rel, max_rel_bound))
+    return (Y, rel) if return_bound else Y
 
 
 def rel_fro_err(approx, exact, A=None):

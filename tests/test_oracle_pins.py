@@ -306,10 +306,84 @@ def test_empty_and_vector_shapes():
 
 def test_svt_gapped_matches_full_jacobi():
     """The compressed route for gapped low-rank + noise inputs equals the
-    full Jacobi oracle (it is the same Eq. (1) on an exact invariant subspace)."""
+    full Jacobi oracle (it is the same Eq. (1) on an exact invariant
+    subspace), and its certificate accepts it."""
     pb = inputs.noisy_lowrank(300, 160, rank=12, idx=5, cfg=inputs.CFG_TEST)
     full = oracle.svt(pb.A, pb.tau)
-    assert relerr(oracle.svt_gapped(pb.A, pb.tau, k=32), full) < 1e-11
+    Y, bound = oracle.svt_gapped(pb.A, pb.tau, k=32, return_bound=True)
+    assert relerr(Y, full) < 1e-11
+    assert bound < 1e-6
     assert relerr(oracle.svt_gapped(pb.A.T, pb.tau, k=32), full.T) < 1e-11
     with pytest.raises(RuntimeError):
         oracle.svt_gapped(pb.A, pb.tau * 1e-3, k=8)   # k too small for this tau
+
+
+def _planted_basis(A, tau, theta, extra=8, j=3, into=20):
+    """Orthonormal basis of the exact top left singular subspace (LAPACK),
+    with column j turned by angle theta towards the noise direction `into`
+    places below the threshold: the subspace misses part of one u_j."""
+    U, s, _ = np.linalg.svd(A, full_matrices=False)
+    r1 = int(np.sum(s > tau))
+    Q = U[:, :r1 + extra].copy()
+    Q[:, j] = math.cos(theta) * U[:, j] + math.sin(theta) * U[:, r1 + into]
+    Q, _ = np.linalg.qr(Q)
+    return Q
+
+
+def test_certificate_rejects_partial_subspace():
+    """A basis that misses part of one retained singular direction passes the
+    residual test ||(I - QQ^T) A||_2 < tau (necessary, not sufficient), yet
+    gives a wrong A_tau; the duality-gap certificate bounds that error from
+    above and rejects it (prox optimality, section 2)."""
+    pb = inputs.noisy_lowrank(300, 160, rank=12, idx=5, cfg=inputs.CFG_TEST)
+    A = pb.A.astype(np.float64)
+    full = oracle.svt(A, pb.tau)
+    for theta in (1e-3, 1e-4):
+        Q = _planted_basis(A, pb.tau, theta)
+        assert np.linalg.norm(A - Q @ (Q.T @ A), 2) * 1.05 < pb.tau   # the old check passes
+        Z = oracle.svt(Q.T @ A, pb.tau)
+        Y = Q @ Z
+        bound, _ = oracle.prox_error_bound(A, Y, pb.tau, factor=(Q, Z))
+        actual = np.linalg.norm(Y - full)
+        assert actual > 1e-5 * np.linalg.norm(full)                   # and the result is wrong
+        assert bound >= actual
+        assert bound > 1e-6 * np.linalg.norm(Y)                       # rejected
+
+
+@pytest.mark.parametrize("kind", ["exact", "scaled", "dense_noise", "low_rank", "dropped_term", "transposed"])
+def test_prox_error_bound_is_an_upper_bound(kind):
+    """The certificate is an upper bound on ||Y - A_tau||_F for any Y, and
+    is small only at A_tau: exact answer (tiny), and planted mistakes (a
+    scaled result, noise, a low-rank slip, a dropped singular triple, the
+    transposed orientation) each give a bound above their true error."""
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((60, 40))
+    s = np.linalg.svd(A, compute_uv=False)
+    tau = float(np.sqrt(s[9] * s[10]))
+    At = oracle.svt(A, tau)
+    U, sv, V = oracle.svd(A)
+    Y = {"exact": At,
+         "scaled": 1.01 * At,
+         "dense_noise": At + 1e-4 * rng.standard_normal(At.shape),
+         "low_rank": At + 1e-3 * np.outer(rng.standard_normal(60), rng.standard_normal(40)),
+         "dropped_term": At - (sv[0] - tau) * np.outer(U[:, 0], V[:, 0]),
+         "transposed": oracle.svt(A.T, tau).T + 1e-6 * np.outer(U[:, 12], V[:, 3])}[kind]
+    bound, parts = oracle.prox_error_bound(A, Y, tau)
+    actual = np.linalg.norm(Y - At)
+    assert bound >= actual * (1 - 1e-9)
+    if kind == "exact":
+        assert bound < 1e-6 * np.linalg.norm(At)
+        assert parts["spec_upper"] <= tau * (1 + 1e-10)
+    else:
+        assert bound > 1e-6 * np.linalg.norm(At)
+
+
+@pytest.mark.slow
+def test_svt_gapped_c3_recipe_matches_full_jacobi():
+    """The precision-form recipe (rank-200 Haar signal, sigma ~ U[1, 10],
+    noise std 0.01/sqrt(n), tau = 2 ||N||_2) at 4096 x 2048: the certified
+    compressed route equals the full Jacobi oracle (about 1.5 min on 8 cores)."""
+    pb = inputs.noisy_lowrank(4096, 2048, rank=200, idx=7, cfg=inputs.CFG_TEST, norm_iters=60)
+    Y, bound = oracle.svt_gapped(pb.A, pb.tau, k=256, return_bound=True)
+    assert bound < 1e-6
+    assert relerr(Y, oracle.svt(pb.A, pb.tau)) < 1e-10
