@@ -113,20 +113,22 @@ def cpu_baseline_leg(problems, results, n_sample, checks):
         errs[pb.name] = {"rel_err": float(err / nref), "rel_err_bound_fp32_input": float((err + delta) / (nref - delta))}
     for check in checks:
         check(oracle)
-    sample = inputs.square_case(0.5, n=n_sample)
+    n_main = problems[0].A.shape[0]
+    if n_sample >= n_main:
+        sample = problems[len(problems) // 2]   # the main workload's own tau = q50 matrix
+    else:
+        sample = inputs.square_case(0.5, n=n_sample)
     t0 = time.perf_counter()
     oracle.svt(sample.A, sample.tau)
     dt = time.perf_counter() - t0
-    scale = (problems[0].A.shape[0] / n_sample) ** 3
-    cpu = {
-        "value": 1.0 / (dt * scale),
-        "unit": "matrices/s",
-        "cores": oracle.threads(),
-        "kind": "oracle",
-        "sample": "one-sided Jacobi SVD + threshold (FP64, OpenMP) of one %dx%d matrix of the same recipe "
-                  "(tau at the 50%% quantile) in %.2f s, scaled by (4096/%d)^3 = %.0f to one 4096x4096 matrix"
-                  % (n_sample, n_sample, dt, n_sample, scale),
-    }
+    scale = (n_main / sample.A.shape[0]) ** 3
+    what = ("one-sided Jacobi SVD + threshold (FP64, OpenMP) of one %dx%d matrix of the main workload "
+            "(tau at the 50%% quantile) in %.2f s" % (sample.A.shape[0], sample.A.shape[1], dt))
+    if scale != 1.0:
+        what += ", scaled by (%d/%d)^3 = %.0f to one %dx%d matrix" % (n_main, sample.A.shape[0], scale, n_main,
+                                                                       n_main)
+    cpu = {"value": 1.0 / (dt * scale), "unit": "matrices/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": what}
     return cpu, errs
 
 
@@ -155,7 +157,8 @@ def precision_leg(psvt, torch, dev, checks, problems=None):
         Y = torch.empty_like(A)
         row = {}
         for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)),
-                         ("split_bf16_all", dict(n_bf16=20, flags=psvt.FLAG_SPLIT_P))]:
+                         ("bf16_plainP", dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P)),
+                         ("split_bf16_all", dict(n_bf16=20))]:
             cfg, _ = psvt.make_config(iters=20, **kw)
             ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, m, n, cfg), dtype=torch.uint8, device=dev)
             ms = time_calls(torch, lambda: psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw), 3)
@@ -177,8 +180,12 @@ def precision_leg(psvt, torch, dev, checks, problems=None):
             if checks is not None:
                 Yh = Y.cpu().numpy().astype(np.float64)
 
-                def check(oracle, pb=pb, Yh=Yh, dst=row[name]):
-                    dst["rel_err"] = oracle.rel_fro_err(Yh, oracle.svt_gapped(pb.A, pb.tau, k=256))
+                def check(oracle, pb=pb, Yh=Yh, dst=row[name], memo={}):
+                    if pb.name not in memo:  # certified compressed reference, once per matrix
+                        memo[pb.name] = oracle.svt_gapped(pb.A, pb.tau, k=256, return_bound=True)
+                    ref, cert = memo[pb.name]
+                    dst["rel_err"] = oracle.rel_fro_err(Yh, ref)
+                    dst["reference_certified_to"] = cert
                 checks.append(check)
         out["%dx%d" % (m, n)] = row
     # the main workload (three 4096^2 constructed matrices, tau at the 10/50/90 %
@@ -187,8 +194,7 @@ def precision_leg(psvt, torch, dev, checks, problems=None):
         As = [torch.from_numpy(pb.A).to(dev) for pb in problems]
         Y = torch.empty_like(As[0])
         row = {}
-        for name, kw in [("bf16_splitP", dict(n_bf16=18, flags=psvt.FLAG_SPLIT_P)),
-                         ("split_bf16_all", dict(n_bf16=20, flags=psvt.FLAG_SPLIT_P))]:
+        for name, kw in [("bf16", dict(n_bf16=18)), ("split_bf16_all", dict(n_bf16=20))]:
             cfg, _ = psvt.make_config(iters=20, **kw)
             ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, *problems[0].A.shape, cfg), dtype=torch.uint8, device=dev)
 
@@ -225,7 +231,8 @@ def batched_leg(psvt, torch, dev, checks, count=512):
     As = [torch.from_numpy(p.A).to(dev) for p in pbs]
     taus = [p.tau for p in pbs]
     out = {"matrices": count}
-    for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)), ("bf16_splitP", dict(n_bf16=18, flags=2))]:
+    for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)),
+                     ("bf16_plainP", dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P))]:
         b = psvt.Batch(As, taus, iters=20, **kw)
         nl, fl = b.stats()
         ms = time_calls(torch, b.run_graph, 3)
@@ -315,9 +322,10 @@ def fig1_leg(psvt, torch, dev, checks, taus=(1.0, 17.0, 33.0), kmax=30):
     from paper_2607_22484_amd import inputs
     A = inputs.gaussian(301, 300, cfg=inputs.CFG_FIG1)
     Ad = torch.from_numpy(A).to(dev)
+    plain = psvt.FLAG_PLAIN_P | psvt.FLAG_PLAIN_S
     scheds = {"fp32": lambda k: {}, "bf16_2fp32": lambda k: {"n_bf16": max(k - 2, 0)},
-              "bf16_splitP_2fp32": lambda k: {"n_bf16": max(k - 2, 0), "flags": psvt.FLAG_SPLIT_P},
-              "bf16": lambda k: {"n_bf16": k}}
+              "bf16_plainP_2fp32": lambda k: {"n_bf16": max(k - 2, 0), "flags": psvt.FLAG_PLAIN_P},
+              "bf16_plain": lambda k: {"n_bf16": k, "flags": plain}}
     outs = {}
     t0 = time.perf_counter()
     for name, kw in scheds.items():
@@ -347,8 +355,8 @@ def fig2_leg(psvt, torch, dev, checks, sizes=(1000, 2000, 3000, 4000, 5000), dra
     iterations, and BF16 throughout (as the paper's experiment).  Accuracy
     of the first 1000 x 1001 draw is filled in by the CPU oracle leg."""
     from paper_2607_22484_amd import inputs
-    scheds = {"fp32": {}, "bf16_splitP_2fp32": {"n_bf16": iters - 2, "flags": psvt.FLAG_SPLIT_P},
-              "bf16": {"n_bf16": iters}}
+    scheds = {"fp32": {}, "bf16_2fp32": {"n_bf16": iters - 2},
+              "bf16_plain": {"n_bf16": iters, "flags": psvt.FLAG_PLAIN_P | psvt.FLAG_PLAIN_S}}
     out = {"iters": iters, "draws": draws, "ms_per_svt": {}}
     keep = {}
     for m in sizes:
@@ -377,65 +385,110 @@ def fig2_leg(psvt, torch, dev, checks, sizes=(1000, 2000, 3000, 4000, 5000), dra
     return out
 
 
-def serving_leg(psvt, torch, dev, rates=(100, 200, 1000, 5000), count=300):
-    """Serving form: Poisson arrivals, sizes 256..4096 square and 2:1, rank
-    r in {16, 64, 256} + noise, 6 FP8 + 12 BF16 + 2 FP32 iterations."""
+def _fingerprint(torch, Y):
+    """A checksum of the bits of Y (position-weighted sum of its int32 words,
+    wrapping in int64): equal results give equal fingerprints."""
+    v = Y.contiguous().view(torch.int32).flatten().to(torch.int64)
+    w = torch.arange(1, v.numel() + 1, device=Y.device, dtype=torch.int64)
+    return (int(v.sum().item()), int((v * w).sum().item()))
+
+
+def serving_leg(psvt, torch, dev, checks, rates=(100, 200, 500, 1000, 2000, 5000), count=2000):
+    """Serving form: Poisson arrivals at each rate, ``count`` requests per
+    rate; short side s = round(exp U[ln 256, ln 4096]), square or 2:1 either
+    way; rank r in {16, 64, 256} (<= s/4) signal + noise of std 0.01/sqrt(n),
+    tau = 2 x 0.01 (sqrt(m) + sqrt(n)) / sqrt(n); 6 FP8 + 12 BF16 + 2 FP32
+    iterations.  Accuracy: every served result is compared bit for bit with
+    the single call of the same schedule on the same request (through a
+    checksum of its bits), and the single calls of one request per size
+    bucket are compared with the certified oracle by the CPU leg."""
     from paper_2607_22484_amd import inputs
     g = torch.Generator(device=dev)
     g.manual_seed(2607)
+    shapes = inputs.serve_shapes(count, idx=0)
     reqs = []
-    for (m, n, r) in inputs.serve_shapes(count, idx=0):
+    for (m, n, r) in shapes:
         U = torch.linalg.qr(torch.randn(m, r, device=dev, generator=g))[0]
         V = torch.linalg.qr(torch.randn(n, r, device=dev, generator=g))[0]
         s = 1.0 + 9.0 * torch.rand(r, device=dev, generator=g)
         A = ((U * s) @ V.T + torch.randn(m, n, device=dev, generator=g) * (0.01 / math.sqrt(n))).contiguous()
         reqs.append((A, 2 * 0.01 * (math.sqrt(m) + math.sqrt(n)) / math.sqrt(n)))
+        del U, V
     torch.cuda.synchronize()
-    out = {}
+    print("[bench] serving: %d requests generated" % len(reqs), file=sys.stderr, flush=True)
+    out = {"requests_per_rate": count, "schedule": "6 FP8 + 12 BF16 (split bf16) + 2 FP32"}
     # the plain FP32 form on the same requests, one matrix per launch sequence
-    sample = reqs
     cfg, _ = psvt.make_config(iters=20)
-    ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, A.shape[0], A.shape[1], cfg) for A, _ in sample),
+    ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, A.shape[0], A.shape[1], cfg) for A, _ in reqs),
                      dtype=torch.uint8, device=dev)
-    Ys = [torch.empty_like(A) for A, _ in sample]
+    Y1 = torch.empty(max(A.numel() for A, _ in reqs), device=dev)
 
     def single():
-        for (A, tau), Y in zip(sample, Ys):
-            psvt.svt(A, tau, iters=20, out=Y, ws=ws)
+        for A, tau in reqs:
+            psvt.svt(A, tau, iters=20, out=Y1[:A.numel()].view(A.shape), ws=ws)
     ms = time_calls(torch, single, 1)
-    out["fp32_single_calls"] = {"requests": len(sample), "matrices_per_s": len(sample) / (ms * 1e-3)}
+    out["fp32_single_calls"] = {"requests": len(reqs), "matrices_per_s": len(reqs) / (ms * 1e-3)}
     del ws
     # the served schedule as single calls, one request at a time (no batching)
     lp = dict(n_fp8=6, n_bf16=12)
     cfg, _ = psvt.make_config(iters=20, **lp)
-    ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, A.shape[0], A.shape[1], cfg) for A, _ in sample),
+    ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, A.shape[0], A.shape[1], cfg) for A, _ in reqs),
                      dtype=torch.uint8, device=dev)
 
     def single_lp():
-        for (A, tau), Y in zip(sample, Ys):
-            psvt.svt(A, tau, iters=20, out=Y, ws=ws, **lp)
+        for A, tau in reqs:
+            psvt.svt(A, tau, iters=20, out=Y1[:A.numel()].view(A.shape), ws=ws, **lp)
     ms = time_calls(torch, single_lp, 1)
-    out["lp_single_calls"] = {"requests": len(sample), "matrices_per_s": len(sample) / (ms * 1e-3)}
-    del ws, Ys
-    # cohort admission (the server's default), and at two rates the eager
-    # joining it replaces
-    runs = [(rate, True) for rate in rates] + [(rate, False) for rate in rates if rate in (200, 5000)]
-    for rate, cohort in runs:
-        srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, iters=20, n_fp8=6, n_bf16=12, cohort=cohort)
+    out["lp_single_calls"] = {"requests": len(reqs), "matrices_per_s": len(reqs) / (ms * 1e-3)}
+    # reference fingerprints of the single calls, and the sampled results
+    buckets = {}
+    for i, (m, n, r) in enumerate(shapes):
+        buckets.setdefault(int(math.log2(min(m, n))), i)
+    sample = sorted(buckets.values())
+    ref_fp, kept = [], {}
+    for i, (A, tau) in enumerate(reqs):
+        Y = Y1[:A.numel()].view(A.shape)
+        psvt.svt(A, tau, iters=20, out=Y, ws=ws, **lp)
+        ref_fp.append(_fingerprint(torch, Y))
+        if i in sample:
+            kept[i] = (A.cpu().numpy(), Y.cpu().numpy().astype(np.float64), tau, shapes[i])
+    del ws, Y1
+    torch.cuda.empty_cache()
+    for rate in rates:
+        srv = psvt.Server(budget_bytes=64 << 30, max_slots=64, iters=20, **lp)
         gaps = np.random.default_rng(rate).exponential(1.0 / rate, size=len(reqs))
         t = time.perf_counter()
+        tickets = []
         for (A, tau), gp in zip(reqs, gaps):
             t += gp
             while time.perf_counter() < t:
                 pass
-            srv.submit(A, tau)
-        srv.drain(timeout=600)
+            tickets.append(srv.submit(A, tau))
+        srv.drain(timeout=900)
         st = srv.stats()
-        out["%d_per_s%s" % (rate, "" if cohort else "_eager")] = {
-            "completed": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "launches": st["launches"],
-            "matrices_per_s": st["matrices_per_s"], "queue_p99_ms": st["queue_p99_ms"],
-            "peak_pool_gib": st["peak_bytes"] / 2 ** 30}
+        same = sum(_fingerprint(torch, Y) == f for (_, Y), f in zip(tickets, ref_fp))
+        out["%d_per_s" % rate] = {
+            "completed": st["completed"], "failed": st["failed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "launches": st["launches"], "matrices_per_s": st["matrices_per_s"], "queue_p99_ms": st["queue_p99_ms"],
+            "peak_pool_gib": st["peak_bytes"] / 2 ** 30, "bitwise_equal_to_single_call": same}
         srv.close()
+        del tickets
+        torch.cuda.empty_cache()
+        print("[bench] serving %d/s: %.1f matrices/s, p50 %.1f ms, p99 %.1f ms, %d/%d bitwise equal"
+              % (rate, st["matrices_per_s"], st["p50_ms"], st["p99_ms"], same, len(reqs)), file=sys.stderr,
+              flush=True)
+    if checks is not None:
+        def check(oracle, dst=out):
+            rows = []
+            for i in sample:
+                A, Y, tau, (m, n, r) = kept[i]
+                ref, cert = oracle.svt_gapped(A, tau, k=r + 64, return_bound=True)
+                rows.append({"shape": [m, n], "rank": r, "rel_err": oracle.rel_fro_err(Y, ref),
+                             "reference_certified_to": cert})
+            dst["sampled_single_call_errors"] = rows
+            dst["worst_sampled_rel_err"] = max(x["rel_err"] for x in rows)
+        checks.append(check)
+    del reqs
     return out
 
 
@@ -447,7 +500,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="size of the matrix the CPU oracle is timed on (the main workload's size: one of its "
+                         "own matrices)")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
     ap.add_argument("--forms", default="small,rank,precision,batched,serving,fig1,fig2",
                     help="comma-separated subset of the small / rank / precision / batched / serving / fig1 / fig2 "
@@ -575,7 +630,8 @@ def main():
             torch.cuda.empty_cache()
         if "serving" in want:
             print("[bench] serving form ...", file=sys.stderr, flush=True)
-            forms["serving"] = serving_leg(psvt, torch, dev)
+            forms["serving"] = serving_leg(psvt, torch, dev, checks)
+            torch.cuda.empty_cache()
         if "fig1" in want:
             print("[bench] error vs iterations (Fig. 1 workload) ...", file=sys.stderr, flush=True)
             forms["fig1_error_vs_iterations"] = fig1_leg(psvt, torch, dev, checks)

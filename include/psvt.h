@@ -59,20 +59,60 @@ enum {
 /* operation ids for psvt_workspace_bytes */
 enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R = 3 };
 
-/* psvt_config.flags.  The sign iteration S works on A^T A - tau^2 I, whose
- * spectrum is the square of A's, so the eigenvalues that decide the sign
- * are far below bfloat16 resolution of the largest one.  By default its
- * low-precision iterations therefore use "split bf16" operands (x = hi + lo,
- * two bf16 planes, products hi.hi + hi.lo + lo.hi: three bf16 MFMA passes,
- * about 16 mantissa bits).
- *   PSVT_FLAG_PLAIN_S  S's low-precision iterations use plain FP8/BF16
- *                      operands (faster, loses the small eigenvalues).
- *   PSVT_FLAG_SPLIT_P  P's BF16 iterations use split bf16 as well (needed
- *                      when tau is close to the retained singular values:
- *                      the error of P enters A_tau multiplied by
- *                      tau / (sigma - tau)). */
+/* psvt_config.flags.
+ *
+ * Low-precision operands.  A BF16 iteration by default uses "split bf16"
+ * operands (x = hi + lo, two bf16 planes, products hi.hi + hi.lo + lo.hi:
+ * three bf16 MFMA passes, about 16 mantissa bits) for both polar factors:
+ *   - S works on A^T A - tau^2 I, whose spectrum is the square of A's, so
+ *     the eigenvalues that decide the sign sit far below bfloat16 resolution
+ *     of the largest one;
+ *   - the error of P enters A_tau multiplied by tau / (sigma - tau), which
+ *     is up to 20 for singular values 5 % above tau.
+ * With split operands the 18 BF16 + 2 FP32 schedule stays within 1e-2 of
+ * the exact A_tau on inputs whose singular values keep a 5 % gap from tau.
+ *   PSVT_FLAG_PLAIN_P  P's BF16 iterations use plain bf16 operands (one MFMA
+ *                      pass).  Faster; the result then carries P's bf16
+ *                      rounding times tau / (sigma - tau): measured up to
+ *                      8e-2 for tau mid-spectrum with a 5 % gap, about 1e-3
+ *                      for tau near the smallest singular values.
+ *   PSVT_FLAG_PLAIN_S  S's BF16 iterations use plain bf16 operands (loses
+ *                      the eigenvalues that decide the sign; not for
+ *                      accuracy below 1e-1).
+ *   PSVT_FLAG_SPLIT_P  accepted for compatibility: split P is the default.
+ * FP8 iterations (n_fp8) use plain e4m3 operands in P and split bf16 in S.
+ * K iterations with plain operands of unit roundoff u (2^-8 bf16, 2^-4
+ * e4m3) leave polar() accurate to about u kappa sqrt(K) in the relative
+ * Frobenius norm, kappa = sigma_max / sigma_min of the input: each such
+ * iteration's rounding is amplified by sigma_max / sigma in the direction of
+ * sigma, and the K contributions add up (measured: 18 plain bf16
+ * iterations 2.0e-2 at kappa = 4; 6 e4m3 iterations 0.2 at kappa = 100).  In svt that error enters multiplied by
+ * tau / (sigma - tau) on the retained directions, so the FP8 schedule suits
+ * inputs whose retained singular values sit far above tau (low rank plus
+ * noise), not tau inside a dense spectrum.
+ *
+ * Status word.  PSVT_FLAG_STATUS: the call also writes *psvt_config.status
+ * (a caller-owned uint32_t in DEVICE memory, written on `stream` after the
+ * output): a bit set of PSVT_STATUS_*.  It costs one norm pass over the
+ * output and, for svt / rank_r / polar_sym, one symmetric s x s product
+ * that measures the sign iteration's convergence:
+ *   PSVT_STATUS_NONFINITE_INPUT   ||input||_F (FP64) is not finite;
+ *   PSVT_STATUS_NONFINITE_OUTPUT  the output has a non-finite entry;
+ *   PSVT_STATUS_NOT_CONVERGED     ||S^2 - I||_F / sqrt(s) > status_tol for
+ *                                 the final sign iterate S (svt, rank_r,
+ *                                 polar_sym; S^2 = I exactly when
+ *                                 converged).  A singular shifted Gram
+ *                                 (tau equal to a singular value, or
+ *                                 tau = 0 with a rank-deficient input) also
+ *                                 sets it. */
 #define PSVT_FLAG_PLAIN_S 0x1u
 #define PSVT_FLAG_SPLIT_P 0x2u
+#define PSVT_FLAG_PLAIN_P 0x4u
+#define PSVT_FLAG_STATUS 0x8u
+
+#define PSVT_STATUS_NONFINITE_INPUT 0x1u
+#define PSVT_STATUS_NONFINITE_OUTPUT 0x2u
+#define PSVT_STATUS_NOT_CONVERGED 0x4u
 
 /* side selection (Proposition 1 and its footnote) */
 enum { PSVT_SIDE_AUTO = 0, PSVT_SIDE_RIGHT = 1, PSVT_SIDE_LEFT = 2 };
@@ -96,7 +136,21 @@ typedef struct psvt_config {
     const double *coeffs;
     /* PSVT_FLAG_* bits; 0 = defaults. */
     uint32_t flags;
-    int32_t reserved[3];
+    int32_t reserved0;
+    /* Safety factor on the spectral bounds that scale each iterate into
+     * the iteration's convergence region: the iterations start from
+     * X / (norm_safety * theta), theta = sqrt(||X^T X||_F) >= sigma_max(X).
+     * theta is already an upper bound (the built-in schedule tolerates 30 %
+     * overshoot), so the default 1 suffices for it; a caller-supplied
+     * schedule designed without margin may ask for more.  0 means 1;
+     * otherwise in [1, 16]. */
+    double norm_safety;
+    /* PSVT_FLAG_STATUS: device pointer to the caller's status word. */
+    uint32_t *status;
+    /* Convergence threshold of PSVT_STATUS_NOT_CONVERGED on the RMS
+     * deviation ||S^2 - I||_F / sqrt(s); 0 means 1e-3. */
+    double status_tol;
+    int32_t reserved[4];
 } psvt_config;
 
 /* Workspace size for `op` on an m x n input (for PSVT_OP_POLAR_SYM, m = n). */
@@ -192,6 +246,11 @@ int psvt_batch_destroy(psvt_batch *batch);
  *            stage).  Setting both is PSVT_EINVAL.
  *   submit:  non-blocking; A is read and Y written by the device at some
  *            later time, so both must stay valid until the request is done.
+ *            `stream` is the caller's stream (hipStream_t, NULL = default)
+ *            that produced A and last used Y: an event recorded on it at
+ *            submit orders the request's first stage after that work (the
+ *            request itself runs on the server's streams).  Results are
+ *            ready once poll / wait report state 2 (done).
  *            PSVT_EWORKSPACE if the request could never fit the budget.
  *   poll / wait:  state 0 queued, 1 running, 2 done, -1 failed.
  *   drain:   waits until nothing is queued or active.
@@ -207,7 +266,7 @@ typedef struct psvt_server_counters {
 } psvt_server_counters;
 int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config *cfg, uint32_t flags,
                        psvt_server **out);
-int psvt_server_submit(psvt_server *server, int op, const psvt_batch_item *item, uint64_t *ticket);
+int psvt_server_submit(psvt_server *server, int op, const psvt_batch_item *item, void *stream, uint64_t *ticket);
 int psvt_server_poll(psvt_server *server, uint64_t ticket, int32_t *state);
 int psvt_server_wait(psvt_server *server, uint64_t ticket, double timeout_s, int32_t *state);
 int psvt_server_drain(psvt_server *server, double timeout_s);

@@ -26,7 +26,8 @@ PSVT_EHIP = -4
 OP_SVT, OP_POLAR, OP_POLAR_SYM, OP_RANK_R = 0, 1, 2, 3
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 DTYPE_F32, DTYPE_BF16, DTYPE_FP8, DTYPE_BF16X3 = 0, 1, 2, 3
-FLAG_PLAIN_S, FLAG_SPLIT_P = 0x1, 0x2
+FLAG_PLAIN_S, FLAG_SPLIT_P, FLAG_PLAIN_P, FLAG_STATUS = 0x1, 0x2, 0x4, 0x8
+STATUS_NONFINITE_INPUT, STATUS_NONFINITE_OUTPUT, STATUS_NOT_CONVERGED = 0x1, 0x2, 0x4
 
 EXPORTED = [
     "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
@@ -57,7 +58,11 @@ class Config(ctypes.Structure):
         ("side", ctypes.c_int32),
         ("coeffs", ctypes.POINTER(ctypes.c_double)),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("reserved0", ctypes.c_int32),
+        ("norm_safety", ctypes.c_double),
+        ("status", ctypes.c_void_p),
+        ("status_tol", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -131,7 +136,7 @@ def load(path: Optional[str] = None):
     srv = ctypes.c_void_p
     lib.psvt_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, cfgp, ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_void_p)]
-    lib.psvt_server_submit.argtypes = [srv, ctypes.c_int, items_p, ctypes.POINTER(ctypes.c_uint64)]
+    lib.psvt_server_submit.argtypes = [srv, ctypes.c_int, items_p, vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.psvt_server_poll.argtypes = [srv, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
     lib.psvt_server_wait.argtypes = [srv, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
     lib.psvt_server_drain.argtypes = [srv, ctypes.c_double]
@@ -158,18 +163,35 @@ def _check(rc: int, where: str):
 
 
 def make_config(iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
-                coeffs: Optional[Sequence[float]] = None, flags: int = 0):
+                coeffs: Optional[Sequence[float]] = None, flags: int = 0, norm_safety: float = 0.0,
+                status=None, status_tol: float = 0.0):
+    """A ``psvt_config``.  ``status``: a 1-element int32/uint32 GPU tensor
+    (or a raw device pointer) that receives the status word; passing it sets
+    FLAG_STATUS."""
     cfg = Config()
-    cfg.flags = int(flags)
     cfg.iters = int(iters)
     cfg.n_fp8 = int(n_fp8)
     cfg.n_bf16 = int(n_bf16)
     cfg.side = int(side)
+    cfg.norm_safety = float(norm_safety)
+    cfg.status_tol = float(status_tol)
+    if status is not None:
+        ptr = status if isinstance(status, int) else _status_ptr(status)
+        cfg.status = ptr
+        flags = int(flags) | FLAG_STATUS
+    cfg.flags = int(flags)
     keep = None
     if coeffs is not None:
         keep = (ctypes.c_double * len(coeffs))(*[float(c) for c in coeffs])
         cfg.coeffs = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
     return cfg, keep
+
+
+def _status_ptr(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.numel() < 1 or t.element_size() != 4:
+        raise TypeError("status must be a GPU tensor with at least one 4-byte element")
+    return t.data_ptr()
 
 
 def workspace_bytes(op: int, m: int, n: int, cfg: Optional[Config] = None) -> int:
@@ -207,10 +229,36 @@ def _workspace(op, m, n, cfg, device, ws=None):
     torch = _torch()
     need = workspace_bytes(op, m, n, cfg)
     if ws is not None:
+        if not isinstance(ws, torch.Tensor):
+            raise TypeError("ws must be a torch.Tensor")
+        if ws.device != device:
+            raise ValueError("ws must live on %s (got %s)" % (device, ws.device))
+        if not ws.is_contiguous():
+            raise ValueError("ws must be contiguous")
         if ws.numel() * ws.element_size() < need:
             raise ValueError("workspace too small: %d < %d bytes" % (ws.numel() * ws.element_size(), need))
         return ws, need
     return torch.empty(max(need, 256), dtype=torch.uint8, device=device), need
+
+
+def _output(out, shape, device, name="out"):
+    """The caller's output buffer, checked before anything is launched: a
+    float32 tensor of exactly `shape` on `device` with unit column stride
+    (the C ABI only sees a pointer and a row stride)."""
+    torch = _torch()
+    if out is None:
+        return torch.empty(shape, dtype=torch.float32, device=device)
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if out.dtype != torch.float32:
+        raise TypeError("%s must be float32 (got %s)" % (name, out.dtype))
+    if tuple(out.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s (got %s)" % (name, tuple(shape), tuple(out.shape)))
+    if out.device != device:
+        raise ValueError("%s must live on %s (got %s)" % (name, device, out.device))
+    if out.numel() > 0 and (out.stride(1) != 1 or (out.shape[0] > 1 and out.stride(0) < out.shape[1])):
+        raise ValueError("%s must be row-major with unit column stride" % name)
+    return out
 
 
 def _ld(A):
@@ -232,70 +280,62 @@ def _ld_any(A):
     return A.stride(0) if A.stride(0) >= cols and A.stride(0) % per16 == 0 else (cols + per16 - 1) // per16 * per16
 
 
-def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
-        coeffs=None, out=None, ws=None, flags: int = 0):
-    """A_tau = U max(Sigma - tau I, 0) V^T via Proposition 1 (FP32 out)."""
+def _method(entry, op, A, tau, out, ws, kwargs, has_tau=True):
+    """One call of a method entry point: checks, output, workspace, then the
+    C call on the current stream of A's device."""
     _check_input(A)
     torch = _torch()
     m, n = A.shape
-    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs, flags)
-    Y = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
+    cfg, keep = make_config(**kwargs)
+    Y = _output(out, (m, n), A.device)
     if m == 0 or n == 0:
         return Y
-    buf, need = _workspace(OP_SVT, m, n, cfg, A.device, ws)
+    buf, need = _workspace(op, m, n, cfg, A.device, ws)
+    args = [A.data_ptr(), m, n, _ld(A)] + ([float(tau)] if has_tau else []) + \
+           [Y.data_ptr(), _ld(Y), buf.data_ptr(), need, ctypes.byref(cfg), _stream_ptr(A)]
     with torch.cuda.device(A.device):
-        _check(load().psvt_svt(A.data_ptr(), m, n, _ld(A), float(tau), Y.data_ptr(), _ld(Y), buf.data_ptr(), need,
-                               ctypes.byref(cfg), _stream_ptr(A)), "psvt_svt")
+        _check(getattr(load(), entry)(*args), entry)
     del keep
     return Y
+
+
+def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
+        coeffs=None, out=None, ws=None, flags: int = 0, norm_safety: float = 0.0, status=None,
+        status_tol: float = 0.0):
+    """A_tau = U max(Sigma - tau I, 0) V^T via Proposition 1 (FP32 out).
+    ``status``: optional 1-element int32 GPU tensor for the status word."""
+    return _method("psvt_svt", OP_SVT, A, tau, out, ws,
+                   dict(iters=iters, n_fp8=n_fp8, n_bf16=n_bf16, side=side, coeffs=coeffs, flags=flags,
+                        norm_safety=norm_safety, status=status, status_tol=status_tol))
 
 
 def rank_r(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
-        coeffs=None, out=None, ws=None, flags: int = 0):
+           coeffs=None, out=None, ws=None, flags: int = 0, norm_safety: float = 0.0, status=None,
+           status_tol: float = 0.0):
     """Best rank-r approximation (Corollary 1), tau between sigma_{r+1} and sigma_r."""
-    _check_input(A)
-    torch = _torch()
-    m, n = A.shape
-    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs, flags)
-    Y = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
-    if m == 0 or n == 0:
-        return Y
-    buf, need = _workspace(OP_RANK_R, m, n, cfg, A.device, ws)
-    with torch.cuda.device(A.device):
-        _check(load().psvt_rank_r(A.data_ptr(), m, n, _ld(A), float(tau), Y.data_ptr(), _ld(Y), buf.data_ptr(),
-                                  need, ctypes.byref(cfg), _stream_ptr(A)), "psvt_rank_r")
-    del keep
-    return Y
+    return _method("psvt_rank_r", OP_RANK_R, A, tau, out, ws,
+                   dict(iters=iters, n_fp8=n_fp8, n_bf16=n_bf16, side=side, coeffs=coeffs, flags=flags,
+                        norm_safety=norm_safety, status=status, status_tol=status_tol))
 
 
 def polar(A, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO, coeffs=None, out=None,
-          ws=None, flags: int = 0):
+          ws=None, flags: int = 0, norm_safety: float = 0.0, status=None):
     """Polar factor U V^T (section 2)."""
-    _check_input(A)
-    torch = _torch()
-    m, n = A.shape
-    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs, flags)
-    P = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=A.device)
-    if m == 0 or n == 0:
-        return P
-    buf, need = _workspace(OP_POLAR, m, n, cfg, A.device, ws)
-    with torch.cuda.device(A.device):
-        _check(load().psvt_polar(A.data_ptr(), m, n, _ld(A), P.data_ptr(), _ld(P), buf.data_ptr(), need,
-                                 ctypes.byref(cfg), _stream_ptr(A)), "psvt_polar")
-    del keep
-    return P
+    return _method("psvt_polar", OP_POLAR, A, None, out, ws,
+                   dict(iters=iters, n_fp8=n_fp8, n_bf16=n_bf16, side=side, coeffs=coeffs, flags=flags,
+                        norm_safety=norm_safety, status=status), has_tau=False)
 
 
 def polar_sym(G, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, coeffs=None, out=None, ws=None,
-              flags: int = 0):
+              flags: int = 0, norm_safety: float = 0.0, status=None, status_tol: float = 0.0):
     """Matrix sign of symmetric G (symmetrised on load)."""
     _check_input(G, "G")
     torch = _torch()
     n, n2 = G.shape
     if n != n2:
         raise ValueError("polar_sym needs a square matrix")
-    cfg, keep = make_config(iters, n_fp8, n_bf16, SIDE_AUTO, coeffs, flags)
-    S = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=G.device)
+    cfg, keep = make_config(iters, n_fp8, n_bf16, SIDE_AUTO, coeffs, flags, norm_safety, status, status_tol)
+    S = _output(out, (n, n), G.device)
     if n == 0:
         return S
     buf, need = _workspace(OP_POLAR_SYM, n, n, cfg, G.device, ws)
@@ -435,19 +475,27 @@ class Server:
         self._pinned = {}
 
     def submit_ptr(self, A_ptr: int, Y_ptr: int, m: int, n: int, lda: int, ldy: int, tau: float,
-                   op: int = OP_SVT) -> int:
+                   op: int = OP_SVT, stream=None) -> int:
+        """Raw submit; ``stream``: the hipStream_t handle (int) whose pending
+        work the request must follow (None = the default stream)."""
         item = BatchItem(A_ptr, Y_ptr, m, n, lda, ldy, float(tau))
         t = ctypes.c_uint64(0)
-        _check(load().psvt_server_submit(self._h, op, ctypes.byref(item), ctypes.byref(t)), "psvt_server_submit")
+        _check(load().psvt_server_submit(self._h, op, ctypes.byref(item), ctypes.c_void_p(stream),
+                                         ctypes.byref(t)), "psvt_server_submit")
         return int(t.value)
 
     def submit(self, A, tau: float, out=None, op: int = OP_SVT):
-        """Submit A (float32 GPU tensor); returns (ticket, Y).  Keep A and Y
-        alive until the ticket is done."""
+        """Submit A (float32 GPU tensor); returns (ticket, Y).  The request
+        is ordered after the work already queued on A's current stream (which
+        may still be producing A).  Keep A and Y alive until the ticket is
+        done."""
         torch = _torch()
         _check_input(A)
-        Y = out if out is not None else torch.empty_like(A)
-        t = self.submit_ptr(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), tau, op)
+        Y = _output(out, tuple(A.shape), A.device)
+        if A.numel() == 0:
+            raise ValueError("empty request")
+        t = self.submit_ptr(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), tau, op,
+                            stream=torch.cuda.current_stream(A.device).cuda_stream)
         self._pinned[t] = (A, Y)
         return t, Y
 

@@ -93,6 +93,9 @@ struct Cfg {
     int side;
     const double *coeffs;
     uint32_t flags;
+    double safety;
+    uint32_t *status;
+    double status_tol;
 };
 
 int read_cfg(const psvt_config *c, Cfg &out) {
@@ -101,6 +104,9 @@ int read_cfg(const psvt_config *c, Cfg &out) {
     out.side = PSVT_SIDE_AUTO;
     out.coeffs = nullptr;
     out.flags = 0;
+    out.safety = 1.0;
+    out.status = nullptr;
+    out.status_tol = 1e-3;
     if (!c) return PSVT_OK;
     if (c->iters < 0 || c->iters > 256) return fail(PSVT_EINVAL, "iters = %d outside 0..256", c->iters);
     if (c->iters) out.iters = c->iters;
@@ -108,8 +114,18 @@ int read_cfg(const psvt_config *c, Cfg &out) {
         return fail(PSVT_EINVAL, "n_fp8 = %d, n_bf16 = %d do not fit in %d iterations", c->n_fp8, c->n_bf16,
                     out.iters);
     if (c->side < 0 || c->side > 2) return fail(PSVT_EINVAL, "side = %d", c->side);
-    if (c->flags & ~(uint32_t)(PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S))
-        return fail(PSVT_EINVAL, "unknown flags 0x%x", c->flags);
+    const uint32_t known = PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S | PSVT_FLAG_PLAIN_P | PSVT_FLAG_STATUS;
+    if (c->flags & ~known) return fail(PSVT_EINVAL, "unknown flags 0x%x", c->flags);
+    if ((c->flags & PSVT_FLAG_SPLIT_P) && (c->flags & PSVT_FLAG_PLAIN_P))
+        return fail(PSVT_EINVAL, "PSVT_FLAG_SPLIT_P and PSVT_FLAG_PLAIN_P exclude each other");
+    if (c->norm_safety != 0.0 && !(c->norm_safety >= 1.0 && c->norm_safety <= 16.0))
+        return fail(PSVT_EINVAL, "norm_safety = %g outside [1, 16]", c->norm_safety);
+    if (c->norm_safety != 0.0) out.safety = c->norm_safety;
+    if ((c->flags & PSVT_FLAG_STATUS) && !c->status) return fail(PSVT_EINVAL, "PSVT_FLAG_STATUS with a NULL status");
+    if (c->status_tol != 0.0 && !(c->status_tol > 0.0 && isfinite(c->status_tol)))
+        return fail(PSVT_EINVAL, "status_tol = %g must be finite and > 0", c->status_tol);
+    if (c->status_tol != 0.0) out.status_tol = c->status_tol;
+    if (c->flags & PSVT_FLAG_STATUS) out.status = c->status;
     out.flags = c->flags;
     out.n_fp8 = c->n_fp8;
     out.n_bf16 = c->n_bf16;
@@ -136,10 +152,13 @@ int iter_dtype(const Cfg &c, int t) {
     return OP_F32;
 }
 
-// P iterations: as scheduled, BF16 as split bf16 when PSVT_FLAG_SPLIT_P.
+// P iterations: FP8 as scheduled; BF16 as split bf16 unless
+// PSVT_FLAG_PLAIN_P (the error of P enters A_tau multiplied by
+// tau / (sigma - tau), up to 20 for a 5 % gap, beyond what plain bf16
+// operands can carry at 1e-2).
 int iter_dtype_P(const Cfg &c, int t) {
     const int d = iter_dtype(c, t);
-    return (d == OP_BF16 && (c.flags & PSVT_FLAG_SPLIT_P)) ? OP_BF16X3 : d;
+    return (d == OP_BF16 && !(c.flags & PSVT_FLAG_PLAIN_P)) ? OP_BF16X3 : d;
 }
 
 // S iterations work on the shifted Gram, whose spectrum is the square of A's:
@@ -388,7 +407,7 @@ hipError_t syrk(const float *A, const float *B, int64_t ld, const float *D, floa
 
 // Gram prelude shared by svt / polar / rank_r: nu, X0, X0^T, T, theta_P.
 int prelude(const float *A, int64_t m, int64_t n, int64_t lda, double tau, const Layout &L, void *ws,
-            Exec &ex, bool want_theta_p) {
+            Exec &ex, bool want_theta_p, double safety) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     double *part = (double *)at(ws, L.part);
     HIP_TRY(ex.norm(make_norm_op(A, m, n, lda, part, sc, NORM_INPUT, tau), "norm of A"), "norm of A");
@@ -410,8 +429,11 @@ int prelude(const float *A, int64_t m, int64_t n, int64_t lda, double tau, const
     g.sc = sc;
     g.sym = 1;
     HIP_TRY(ex.gemm(g, OP_F32, "Gram"), "Gram");
-    if (want_theta_p)
-        HIP_TRY(ex.norm(make_norm_op(F(ws, L.T), L.s, L.s, L.ldS, part, sc, NORM_THETA_P, 0.0), "theta_P"), "theta_P");
+    if (want_theta_p) {
+        NormOp op = make_norm_op(F(ws, L.T), L.s, L.s, L.ldS, part, sc, NORM_THETA_P, 0.0);
+        op.safety = safety;
+        HIP_TRY(ex.norm(op, "theta_P"), "theta_P");
+    }
     return PSVT_OK;
 }
 
@@ -664,13 +686,57 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, bool want
 }
 
 // H = T - (tau/nu)^2 I, R = H^2, theta_S
-int shifted_gram(const Layout &L, void *ws, Exec &ex) {
+int shifted_gram(const Layout &L, void *ws, Exec &ex, double safety) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     double *part = (double *)at(ws, L.part);
     HIP_TRY(ex.tile(make_shift_copy(F(ws, L.T), L.s, L.ldS, F(ws, L.H), L.ldS, sc), "shift"), "shift");
     HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, L.s, 1.0f, -1, 0.0f, -1, 0.0f, sc, ex),
             "H^2");
-    HIP_TRY(ex.norm(make_norm_op(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_THETA_S, 0.0), "theta_S"), "theta_S");
+    NormOp op = make_norm_op(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_THETA_S, 0.0);
+    op.safety = safety;
+    HIP_TRY(ex.norm(op, "theta_S"), "theta_S");
+    return PSVT_OK;
+}
+
+// Status word (PSVT_FLAG_STATUS), after the output is written.  sign: the
+// final sign iterate as Pi = (I + S)/2 (pi = true) or S itself, s x s in
+// the workspace or the caller's buffer; its convergence is measured as
+// ||S^2 - I||_F / sqrt(s) (= 4 ||Pi^2 - Pi||_F / sqrt(s)) with the square
+// written to the R buffer (free once the sign iterations are done).  Then
+// a norm pass over the output checks it for non-finite entries and writes
+// the word.
+int status_stages(const Cfg &c, const Layout &L, void *ws, Exec &ex, const float *sign, int64_t ld_sign, bool pi,
+                  const float *out, int64_t rows, int64_t cols, int64_t ld_out) {
+    if (!c.status) return PSVT_OK;
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    double *part = (double *)at(ws, L.part);
+    double tol = -1.0;
+    if (sign) {
+        GemmArgs g = gemm_defaults();
+        g.A = g.B = sign;
+        g.lda = g.ldb = ld_sign;
+        g.C = F(ws, L.R);
+        g.ldc = L.ldS;
+        g.M = g.N = g.K = (int)L.s;
+        g.sc = sc;
+        g.sym = 1;
+        if (pi) {  // Pi^2 - Pi
+            g.D = sign;
+            g.ldd = ld_sign;
+            g.beta = -1.0f;
+        } else {   // S^2 - I
+            g.diag = -1.0f;
+        }
+        HIP_TRY(ex.gemm(g, OP_F32, "status: S^2 - I"), "status: S^2 - I");
+        NormOp op = make_norm_op(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_CONV, 0.0);
+        op.scale = (pi ? 4.0 : 1.0) / sqrt((double)L.s);
+        HIP_TRY(ex.norm(op, "status: convergence"), "status: convergence");
+        tol = c.status_tol;
+    }
+    NormOp op = make_norm_op(out, rows, cols, ld_out, part, sc, NORM_STATUS, 0.0);
+    op.status = c.status;
+    op.tol = tol;
+    HIP_TRY(ex.norm(op, "status"), "status");
     return PSVT_OK;
 }
 
@@ -749,8 +815,8 @@ hipError_t launch_stage(const Stage &s, hipStream_t st) {
 int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
                   void *ws, const Layout &L, const Cfg &c, Exec &ex) {
     int rc;
-    if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, op == PSVT_OP_SVT))) return rc;
-    if ((rc = shifted_gram(L, ws, ex))) return rc;
+    if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, op == PSVT_OP_SVT, c.safety))) return rc;
+    if ((rc = shifted_gram(L, ws, ex, c.safety))) return rc;
     const float *P = nullptr, *Pi = nullptr;
     SideStream *side = nullptr;
     if (L.fork && !ex.rec && (side = side_stream())) {
@@ -790,7 +856,8 @@ int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, dou
         HIP_TRY(hipStreamWaitEvent(ex.st, side->join, 0), "join");
     }
     if (rc) return rc;
-    return final_product(L, ws, P, tau, Pi, Y, ldy, ex);
+    if ((rc = final_product(L, ws, P, tau, Pi, Y, ldy, ex))) return rc;
+    return status_stages(c, L, ws, ex, Pi, L.ldS, true, Y, m, n, ldy);
 }
 
 int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
@@ -830,6 +897,9 @@ int plan_request(int op, const psvt_batch_item &it, void *ws, const psvt_config 
     Cfg c;
     int rc = read_cfg(cfg, c);
     if (rc) return rc;
+    if (c.status)
+        return fail(PSVT_EINVAL, "PSVT_FLAG_STATUS names one status word per call: not for batch items or served "
+                                 "requests (psvt_svt_batched takes one per descriptor)");
     Layout L = make_layout(op, it.m, it.n, c, chains != nullptr);
     *ws_bytes = L.total;
     if (!ws) return PSVT_OK;
@@ -895,8 +965,9 @@ int psvt_polar(const float *A, int64_t m, int64_t n, int64_t lda, float *P, int6
     if ((rc = check_device())) return rc;
     Exec ex;
     ex.st = (hipStream_t)stream;
-    if ((rc = prelude(A, m, n, lda, 0.0, L, ws, ex, true))) return rc;
-    return polar_iterations(c, L, ws, ex, P, ldp, nullptr);
+    if ((rc = prelude(A, m, n, lda, 0.0, L, ws, ex, true, c.safety))) return rc;
+    if ((rc = polar_iterations(c, L, ws, ex, P, ldp, nullptr))) return rc;
+    return status_stages(c, L, ws, ex, nullptr, 0, false, P, m, n, ldp);
 }
 
 int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds, void *ws, size_t ws_bytes,
@@ -922,8 +993,11 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
     HIP_TRY(ex.tile(make_symmetrize_scale(G, n, ldg, F(ws, L.H), L.ldS, sc), "symmetrize"), "symmetrize");
     HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, n, 1.0f, -1, 0.0f, -1, 0.0f, sc, ex),
             "G^2");
-    HIP_TRY(ex.norm(make_norm_op(F(ws, L.R), n, n, L.ldS, part, sc, NORM_THETA_S, 0.0), "theta_S"), "theta_S");
-    return sign_iterations(c, L, ws, ex, false, S, lds, nullptr);
+    NormOp th = make_norm_op(F(ws, L.R), n, n, L.ldS, part, sc, NORM_THETA_S, 0.0);
+    th.safety = c.safety;
+    HIP_TRY(ex.norm(th, "theta_S"), "theta_S");
+    if ((rc = sign_iterations(c, L, ws, ex, false, S, lds, nullptr))) return rc;
+    return status_stages(c, L, ws, ex, S, lds, false, S, n, n, lds);
 }
 
 int psvt_gemm_nt(int dtype, const void *A, int64_t lda, const void *B, int64_t ldb, const float *D, int64_t ldd,

@@ -23,6 +23,7 @@ enum DScalarIdx {
     D_NU = 0,     // ||input||_F
     D_SHIFT = 1,  // (tau / nu)^2: the Gram shift in the scaled problem
     D_NORM = 2,   // last norm reduced
+    D_CONV = 3,   // RMS deviation ||S^2 - I||_F / sqrt(s) of the final sign iterate
     D_COUNT = 8
 };
 
@@ -78,6 +79,10 @@ struct NormOp {
     Scalars *sc;
     int mode;
     double tau;
+    double safety;     // NORM_THETA_*: theta is multiplied by it (>= 1)
+    double scale;      // NORM_CONV: D_CONV = scale * norm
+    uint32_t *status;  // NORM_STATUS: caller's status word (device)
+    double tol;        // NORM_STATUS: convergence threshold on D_CONV (< 0: no check)
 };
 
 // One 64x64-tiled elementwise pass (see kernels.hip, tile ops).
@@ -150,8 +155,13 @@ enum NormMode {
     NORM_INPUT = 0,    // D_NU, D_SHIFT (needs tau), F_INV_NU, F_NU
     NORM_THETA_P = 1,  // F_P1, F_P2, F_P4 from theta = sqrt(norm)
     NORM_THETA_S = 2,  // F_S1, F_S2, F_S4
-    NORM_ONLY = 3      // D_NORM only
+    NORM_ONLY = 3,     // D_NORM only
+    NORM_CONV = 4,     // D_CONV = scale * norm
+    NORM_STATUS = 5    // norm of the output; writes the status word (below)
 };
+
+// Bits of the status word (the values of PSVT_STATUS_* in psvt.h).
+enum StatusBits { ST_NONFINITE_INPUT = 1, ST_NONFINITE_OUTPUT = 2, ST_NOT_CONVERGED = 4 };
 
 constexpr int NORM_PARTIALS = 1024;
 

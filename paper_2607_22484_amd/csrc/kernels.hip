@@ -159,12 +159,20 @@ __device__ __forceinline__ void fro_final_body(const NormOp &op, double *red) {
         // theta = sqrt(||M||_F) bounds the spectral radius of the iterate:
         // M = X^T X (or H^2) has eigenvalues mu_i >= 0 and
         // ||M||_F = sqrt(sum mu_i^2) >= mu_max = sigma_max^2.
-        const double theta = sqrt(nrm);
+        const double theta = sqrt(nrm) * op.safety;
         const int base = op.mode == NORM_THETA_P ? F_P1 : F_S1;
         const double it = theta > 0.0 ? 1.0 / theta : 0.0;
         sc->f[base] = (float)it;
         sc->f[base + 1] = (float)(it * it);
         sc->f[base + 2] = (float)(it * it * it * it);
+    } else if (op.mode == NORM_CONV) {
+        sc->d[D_CONV] = op.scale * nrm;
+    } else if (op.mode == NORM_STATUS) {
+        uint32_t st = 0;
+        if (!isfinite(sc->d[D_NU])) st |= ST_NONFINITE_INPUT;
+        if (!isfinite(nrm)) st |= ST_NONFINITE_OUTPUT;
+        if (op.tol >= 0.0 && !(sc->d[D_CONV] <= op.tol)) st |= ST_NOT_CONVERGED;
+        *op.status = st;
     }
 }
 
@@ -212,6 +220,10 @@ NormOp make_norm_op(const float *X, int64_t rows, int64_t cols, int64_t ld, doub
     op.sc = sc;
     op.mode = mode;
     op.tau = tau;
+    op.safety = 1.0;
+    op.scale = 1.0;
+    op.status = nullptr;
+    op.tol = -1.0;
     return op;
 }
 

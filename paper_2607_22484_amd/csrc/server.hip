@@ -112,6 +112,10 @@ struct Request {
     size_t cut[3] = {0, 0, 0};
     size_t cursor = 0, curP = 0, curS = 0;
     int state = RQ_QUEUED;
+    // recorded on the submitter's stream at submit: the request's first
+    // stage waits for it, so A and Y are ordered after the caller's work
+    hipEvent_t ready = nullptr;
+    bool waited = false;       // the lane stream already waits for `ready`
     bool parked = false;       // admitted, waiting for the lane's next cohort
     int64_t finish_tick = -1;  // lane tick that launched the last stage
     int lane = 0;
@@ -185,6 +189,7 @@ struct psvt_server {
         std::vector<hipEvent_t> seg_event;
         std::vector<int64_t> seg_tick;
         int64_t tick = 0;
+        size_t rr = 0;  // rotation of the runnable list when a tick cannot take them all
         char *ring_host = nullptr, *ring_dev = nullptr;
     };
     Lane lanes[kLanes];
@@ -200,6 +205,7 @@ struct psvt_server {
     bool stop = false;
     std::thread worker;
     int error = PSVT_OK;
+    std::vector<hipEvent_t> free_events;  // ready events of finished requests
 
     // statistics
     int64_t submitted = 0, completed = 0, failed = 0, ticks = 0, launches = 0;
@@ -314,6 +320,10 @@ int launch_tick(psvt_server *s, psvt_server::Lane &lane, int seg, size_t seg_use
 void finish(psvt_server *s, Request *r, int state) {
     r->state = state;
     r->t_done = now_s();
+    if (r->ready) {  // complete: the lane waited for it before the request's first stage
+        s->free_events.push_back(r->ready);
+        r->ready = nullptr;
+    }
     if (s->pool) s->pool->release(r->ws_off, r->ws_bytes);
     r->plan.clear();
     r->plan.shrink_to_fit();
@@ -403,6 +413,24 @@ void worker_main(psvt_server *s) {
             }
             if (runnable.empty()) continue;
             any_runnable = true;
+            // one tick's descriptors must fit its segment: a round takes at
+            // most two stages per request (descriptor + prefix entry each,
+            // GemmArgs the largest descriptor) plus two 256-byte alignments
+            // per group, and a round has at most 80 group keys (products:
+            // 4 operand types x sym x two-operand x 4 tiles, norms, 4 tile
+            // kinds); requests beyond that wait for the lane's next tick
+            // (taken in rotation, so none waits for ever)
+            static_assert(sizeof(GemmArgs) >= sizeof(NormOp) && sizeof(GemmArgs) >= sizeof(TileOp),
+                          "GemmArgs is the largest descriptor");
+            const size_t per_req = 2 * (sizeof(GemmArgs) + sizeof(int)) * (size_t)s->rounds;
+            const size_t fixed = 2 * 256 * 80 * (size_t)s->rounds;
+            const size_t cap = (psvt_server::kSegBytes - fixed) / per_req;
+            if (runnable.size() > cap) {
+                std::vector<Request *> win;
+                for (size_t k = 0; k < cap; ++k) win.push_back(runnable[(ln.rr + k) % runnable.size()]);
+                ln.rr = (ln.rr + cap) % runnable.size();
+                runnable.swap(win);
+            }
             // reuse the lane's oldest segment only once its tick has finished
             const int seg = (int)(ln.tick % s->nseg);
             if (!s->fake && ln.seg_tick[seg] >= 0 && hipEventQuery(ln.seg_event[seg]) != hipSuccess) continue;
@@ -416,6 +444,13 @@ void worker_main(psvt_server *s) {
                 if (rr.empty()) break;
                 rc = build_round(s, ln, rr, seg, seg_used, gl);
             }
+            if (rc == PSVT_OK && !s->fake)
+                for (Request *r : runnable)
+                    if (r->ready && !r->waited) {
+                        const hipError_t e = hipStreamWaitEvent(ln.stream, r->ready, 0);
+                        if (e != hipSuccess) rc = set_error(PSVT_EHIP, hipGetErrorString(e));
+                        r->waited = true;
+                    }
             if (rc == PSVT_OK) rc = launch_tick(s, ln, seg, seg_used, gl);
             if (!s->fake) {
                 (void)hipEventRecord(ln.seg_event[seg], ln.stream);
@@ -427,7 +462,10 @@ void worker_main(psvt_server *s) {
             ++ln.tick;
             launched = true;
             if (rc != PSVT_OK) {
+                // the lane's earlier ticks may still use these workspaces:
+                // release them only once the lane's stream is idle
                 s->error = rc;
+                if (!s->fake) (void)hipStreamSynchronize(ln.stream);
                 for (Request *r : runnable) {
                     finish(s, r, RQ_FAILED);
                     s->active.erase(std::find(s->active.begin(), s->active.end(), r));
@@ -468,6 +506,8 @@ int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config
         return set_error(PSVT_EINVAL, "unknown server flags");
     if ((flags & PSVT_SERVER_COHORT) && (flags & PSVT_SERVER_EAGER))
         return set_error(PSVT_EINVAL, "PSVT_SERVER_COHORT and PSVT_SERVER_EAGER exclude each other");
+    if (cfg && (cfg->flags & PSVT_FLAG_STATUS))
+        return set_error(PSVT_EINVAL, "PSVT_FLAG_STATUS names one status word per call, not per server");
     psvt_server *s = new psvt_server();
     s->fake = (flags & PSVT_SERVER_FAKE) != 0;
     s->cohort = (flags & PSVT_SERVER_EAGER) == 0;
@@ -518,7 +558,7 @@ int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config
     return PSVT_OK;
 }
 
-int psvt_server_submit(psvt_server *s, int op, const psvt_batch_item *item, uint64_t *ticket) {
+int psvt_server_submit(psvt_server *s, int op, const psvt_batch_item *item, void *stream, uint64_t *ticket) {
     if (!s || !item || !ticket) return set_error(PSVT_EINVAL, "NULL argument");
     if (op != PSVT_OP_SVT && op != PSVT_OP_RANK_R) return set_error(PSVT_EINVAL, "op must be svt or rank_r");
     const psvt_batch_item &it = *item;
@@ -545,6 +585,23 @@ int psvt_server_submit(psvt_server *s, int op, const psvt_batch_item *item, uint
         if (s->stop) {
             delete r;
             return set_error(PSVT_EINVAL, "server is shutting down");
+        }
+        if (!s->fake) {
+            hipEvent_t ev = nullptr;
+            hipError_t e = hipSuccess;
+            if (!s->free_events.empty()) {
+                ev = s->free_events.back();
+                s->free_events.pop_back();
+            } else {
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            }
+            if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)stream);
+            if (e != hipSuccess) {
+                if (ev) s->free_events.push_back(ev);
+                delete r;
+                return set_error(PSVT_EHIP, hipGetErrorString(e));
+            }
+            r->ready = ev;
         }
         r->ticket = s->next_ticket++;
         s->all[r->ticket] = r;
@@ -631,7 +688,12 @@ int psvt_server_destroy(psvt_server *s) {
     } else {
         free(s->ring_host);
     }
-    for (auto &kv : s->all) delete kv.second;
+    for (auto &kv : s->all) {
+        if (kv.second->ready) s->free_events.push_back(kv.second->ready);
+        delete kv.second;
+    }
+    if (!s->fake)
+        for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
     delete s->pool;
     delete s;
     return PSVT_OK;

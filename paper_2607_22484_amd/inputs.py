@@ -187,20 +187,20 @@ def gaussian(m: int, n: int, cfg: int = CFG_FIG1, idx: int = 0) -> np.ndarray:
 
 
 def serve_shapes(count: int, idx: int = 0, lo: int = 256, hi: int = 4096):
-    """Request shapes for the serving stream: s log-uniform in [lo, hi]
-    (rounded to a multiple of 16), square, or 2:1 rectangular either way with
-    equal probability; rank r from {16, 64, 256} capped at s/4."""
+    """Request shapes for the serving stream: s = round(exp U[ln lo, ln hi]),
+    square, or 2:1 rectangular either way with equal probability; rank r
+    from {16, 64, 256} capped at s/4."""
     rng = rng_for(CFG_SERVE, idx)
     out = []
     for _ in range(count):
-        s = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi))) / 16.0)) * 16
+        s = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
         kind = rng.integers(0, 3)
         if kind == 0:
             m, n = s, s
         elif kind == 1:
-            m, n = s, max(16, s // 2)
+            m, n = s, max(1, s // 2)
         else:
-            m, n = max(16, s // 2), s
+            m, n = max(1, s // 2), s
         r = int(min(rng.choice([16, 64, 256]), min(m, n) // 4))
         out.append((m, n, max(r, 1)))
     return out

@@ -108,8 +108,41 @@ def test_config_validation():
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
     cfg, keep = psvt.make_config(iters=2, coeffs=[1.0, 0.0, float("nan"), 1, 0, 0])
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
-    cfg, _ = psvt.make_config(flags=0x4)
+    cfg, _ = psvt.make_config(flags=0x10)            # unknown flag
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    cfg, _ = psvt.make_config(flags=psvt.FLAG_SPLIT_P | psvt.FLAG_PLAIN_P)
+    assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    cfg, _ = psvt.make_config(flags=psvt.FLAG_STATUS)  # status flag without a status word
+    assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    for safety in (0.5, 17.0, float("nan")):
+        cfg, _ = psvt.make_config(norm_safety=safety)
+        assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    for tol in (-1.0, float("inf")):
+        cfg, _ = psvt.make_config(status=1 << 40, status_tol=tol)
+        assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    # accepted settings reach the workspace check (ws = NULL here)
+    for kw in (dict(flags=psvt.FLAG_PLAIN_P), dict(norm_safety=1.5), dict(status=1 << 40, status_tol=1e-4)):
+        cfg, _ = psvt.make_config(**kw)
+        assert call_svt(cfg=cfg, ws=None) == psvt.PSVT_EWORKSPACE, kw
+
+
+def test_config_struct_layout():
+    """The binding's Config mirrors psvt_config (size and field offsets as a
+    C compiler lays them out)."""
+    import subprocess
+    import tempfile
+    src = (b'#include <stddef.h>\n#include <stdio.h>\n#include "psvt.h"\nint main(void){printf("%zu %zu %zu %zu %zu\\n",'
+           b' sizeof(psvt_config), offsetof(psvt_config, flags), offsetof(psvt_config, norm_safety),'
+           b' offsetof(psvt_config, status), offsetof(psvt_config, status_tol)); return 0;}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        with open(c, "wb") as f:
+            f.write(src)
+        exe = os.path.join(d, "l")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        got = [int(x) for x in subprocess.check_output([exe]).split()]
+    C = psvt.Config
+    assert got == [ctypes.sizeof(C), C.flags.offset, C.norm_safety.offset, C.status.offset, C.status_tol.offset]
 
 
 def test_empty_is_noop():

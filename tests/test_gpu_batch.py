@@ -32,8 +32,8 @@ def _batch(count, lo, hi, idx):
     return inputs.batch_cases(count=count, idx=idx, lo=lo, hi=hi)
 
 
-@pytest.mark.parametrize("sched", [dict(), dict(n_bf16=18), dict(n_bf16=18, flags=2)],
-                         ids=["fp32", "bf16", "bf16_splitP"])
+@pytest.mark.parametrize("sched", [dict(), dict(n_bf16=18), dict(n_bf16=18, flags=4)],
+                         ids=["fp32", "bf16", "bf16_plainP"])
 def test_batch_equals_single_calls(gpu_lib, tdev, sched):
     """A grouped launch computes every tile exactly as the single-matrix
     launch with the same tile configuration: results are bitwise equal."""

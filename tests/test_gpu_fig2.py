@@ -22,7 +22,7 @@ def test_gaussian_m_by_m_plus_1(gpu_lib, m):
     ref = oracle.svt(A, tau)
     Ad = torch.from_numpy(A).to("cuda:0")
     got = {}
-    for name, kw, tol in [("fp32", {}, 1e-3), ("bf16_splitP", {"n_bf16": 23, "flags": gpu_lib.FLAG_SPLIT_P}, 1e-2)]:
+    for name, kw, tol in [("fp32", {}, 1e-3), ("bf16", {"n_bf16": 23}, 1e-2)]:
         Y = gpu_lib.svt(Ad, tau, iters=25, **kw)
         torch.cuda.synchronize()
         got[name] = oracle.rel_fro_err(Y.cpu().numpy().astype(np.float64), ref)

@@ -80,3 +80,31 @@ def test_budget_admission_on_device(gpu_lib, tdev):
     assert st["completed"] == len(pbs) and st["peak_bytes"] <= budget
     for (_, Y), p in zip(outs, pbs):
         assert oracle.rel_fro_err(Y.cpu().numpy().astype(np.float64), oracle.svt(p.A, p.tau)) <= 1e-2
+
+
+def test_submit_is_ordered_after_the_callers_stream(gpu_lib, tdev):
+    """A request submitted right after in-stream work that writes its input
+    (no synchronisation in between) reads the written input: the server
+    waits for an event recorded on the caller's stream at submit.  The
+    caller's stream is kept busy first, so an unordered read would see the
+    stale contents (zeros)."""
+    torch, dev = tdev
+    pb = inputs.noisy_lowrank(384, 256, rank=16, idx=7, cfg=inputs.CFG_SERVE)
+    _announce("serve submit ordering")
+    src = torch.from_numpy(pb.A).to(dev)
+    single = gpu_lib.svt(src, pb.tau, **SCHED)
+    torch.cuda.synchronize()
+    srv = gpu_lib.Server(budget_bytes=1 << 30, max_slots=4, **SCHED)
+    for trial in range(3):
+        A = torch.zeros_like(src)
+        big = torch.randn(4096, 4096, device=dev)
+        torch.cuda.synchronize()
+        for _ in range(8):                # ~ tens of ms of queued work on the caller's stream
+            big = big @ big
+            big = big / big.norm()
+        A.copy_(src)                      # the input is written only after that work
+        t, Y = srv.submit(A, pb.tau)      # no synchronisation
+        assert srv.wait(t, timeout=60) == gpu_lib.RQ_DONE
+        torch.cuda.synchronize()
+        assert torch.equal(Y, single), trial
+    srv.close()

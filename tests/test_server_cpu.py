@@ -151,3 +151,27 @@ def test_eager_admission_completes_everything():
     srv.drain(timeout=60)
     assert all(srv.poll(t) == psvt.RQ_DONE for t in tickets)
     srv.close()
+
+
+@pytest.mark.parametrize("cohort", [True, False])
+def test_many_same_lane_requests_share_ticks(cohort):
+    """1200 requests of one size class, all admitted at once (more than one
+    tick's descriptor segment can describe): ticks take them in rotation,
+    every request completes and none fails."""
+    srv = psvt.Server(budget_bytes=64 << 30, max_slots=2000, fake=True, cohort=cohort)
+    tickets = [submit(srv, 96, 64) for _ in range(1200)]
+    srv.drain(timeout=120)
+    st = srv.stats()
+    assert st["completed"] == 1200 and st["failed"] == 0
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in tickets)
+    srv.close()
+
+
+def test_status_flag_rejected_for_served_requests():
+    """The status word is one per call: a server config asking for it is
+    rejected at creation."""
+    import ctypes
+    cfg, _ = psvt.make_config(status=1 << 40)
+    h = ctypes.c_void_p()
+    assert psvt.load().psvt_server_create(1 << 30, 4, ctypes.byref(cfg), psvt.SERVER_FAKE,
+                                          ctypes.byref(h)) == psvt.PSVT_EINVAL
