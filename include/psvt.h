@@ -174,6 +174,19 @@ int psvt_polar(const float *A, int64_t m, int64_t n, int64_t lda, float *P, int6
 int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds, void *ws, size_t ws_bytes,
                    const psvt_config *cfg, void *stream);
 
+/* psvt_svt without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments as psvt_svt minus the workspace,
+ * same kernels and results; the workspace is a static device array of
+ * PSVT_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs
+ * on until the process ends (enough for every schedule up to 1024 x 1024;
+ * larger problems return PSVT_EWORKSPACE).  Every launch goes to `stream`
+ * (no side stream).  Calls that overlap in time on one device share the
+ * array and race: serialise them (one stream, or events). */
+#define PSVT_NOALLOC_SCRATCH_BYTES (96u << 20)
+int psvt_svt_noalloc(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
+                     const psvt_config *cfg, void *stream);
+
 /* Best rank-r approximation [A]_r (Corollary 1): with S = polar(A^T A -
  * tau^2 I), [A]_r = (A + A S)/2 = A (I + S)/2 (left-sided form for wide A).
  * tau must lie strictly between sigma_{r+1} and sigma_r (descending order). */

@@ -30,7 +30,7 @@ FLAG_PLAIN_S, FLAG_SPLIT_P, FLAG_PLAIN_P, FLAG_STATUS = 0x1, 0x2, 0x4, 0x8
 STATUS_NONFINITE_INPUT, STATUS_NONFINITE_OUTPUT, STATUS_NOT_CONVERGED = 0x1, 0x2, 0x4
 
 EXPORTED = [
-    "psvt_workspace_bytes", "psvt_svt", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
+    "psvt_workspace_bytes", "psvt_svt", "psvt_svt_noalloc", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
     "psvt_strerror", "psvt_last_error", "psvt_version", "psvt_trace_begin", "psvt_trace_end",
     "psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick",
     "psvt_batch_workspace_bytes", "psvt_batch_create", "psvt_batch_run", "psvt_batch_run_graph", "psvt_batch_stats",
@@ -103,6 +103,8 @@ def load(path: Optional[str] = None):
     lib.psvt_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, cfgp, ctypes.POINTER(ctypes.c_size_t)]
     lib.psvt_svt.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
     lib.psvt_rank_r.argtypes = [vp, i64, i64, i64, f64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
+    lib.psvt_svt_noalloc.argtypes = [vp, i64, i64, i64, f64, vp, i64, cfgp, vp]
+    lib.psvt_svt_noalloc.restype = ctypes.c_int
     lib.psvt_polar.argtypes = [vp, i64, i64, i64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
     lib.psvt_polar_sym.argtypes = [vp, i64, i64, vp, i64, vp, ctypes.c_size_t, cfgp, vp]
     lib.psvt_gemm_nt.argtypes = [ctypes.c_int, vp, i64, vp, i64, vp, i64, vp, i64, i64, i64, i64, ctypes.c_float,
@@ -307,6 +309,27 @@ def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: i
     return _method("psvt_svt", OP_SVT, A, tau, out, ws,
                    dict(iters=iters, n_fp8=n_fp8, n_bf16=n_bf16, side=side, coeffs=coeffs, flags=flags,
                         norm_safety=norm_safety, status=status, status_tol=status_tol))
+
+
+def svt_noalloc(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
+                coeffs=None, out=None, flags: int = 0, norm_safety: float = 0.0, status=None,
+                status_tol: float = 0.0):
+    """svt through psvt_svt_noalloc: the library's static device scratch
+    instead of a workspace (no device allocation by the library; the output
+    is allocated here unless ``out`` is given).  Sizes up to the scratch
+    capacity (PSVT_NOALLOC_SCRATCH_BYTES, every schedule up to 1024^2)."""
+    _check_input(A)
+    torch = _torch()
+    m, n = A.shape
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, coeffs, flags, norm_safety, status, status_tol)
+    Y = _output(out, (m, n), A.device)
+    if m == 0 or n == 0:
+        return Y
+    with torch.cuda.device(A.device):
+        _check(load().psvt_svt_noalloc(A.data_ptr(), m, n, _ld(A), float(tau), Y.data_ptr(), _ld(Y),
+                                       ctypes.byref(cfg), _stream_ptr(A)), "psvt_svt_noalloc")
+    del keep
+    return Y
 
 
 def rank_r(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,

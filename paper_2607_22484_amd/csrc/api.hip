@@ -860,8 +860,11 @@ int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, dou
     return status_stages(c, L, ws, ex, Pi, L.ldS, true, Y, m, n, ldy);
 }
 
+// single: a stand-alone call that may fork P's iterations to the calling
+// thread's side stream (creating it on first use); false keeps every launch
+// on the caller's stream and creates nothing.
 int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
-             void *ws, size_t ws_bytes, const psvt_config *cfg, void *stream) {
+             void *ws, size_t ws_bytes, const psvt_config *cfg, void *stream, bool single = true) {
     g_last_error.clear();
     Cfg c;
     int rc = read_cfg(cfg, c);
@@ -870,7 +873,7 @@ int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double t
     if ((rc = check_matrix(Y, m, n, ldy, "Y"))) return rc;
     if (!(tau >= 0.0) || !isfinite(tau)) return fail(PSVT_EINVAL, "tau must be finite and >= 0");
     if (m == 0 || n == 0) return PSVT_OK;
-    Layout L = make_layout(op, m, n, c, true);
+    Layout L = make_layout(op, m, n, c, single);
     if ((rc = check_ws(ws, ws_bytes, L))) return rc;
     if (overlaps(Y, span_bytes(m, n, ldy), A, span_bytes(m, n, lda)) ||
         overlaps(Y, span_bytes(m, n, ldy), ws, L.total) || overlaps(A, span_bytes(m, n, lda), ws, L.total))
@@ -886,6 +889,23 @@ int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double t
 namespace psvt {
 
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+// svt on a given workspace with every launch on `stream` (no side stream):
+// the entry point without allocation runs through here.
+int svt_on_workspace(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
+                     void *ws, size_t ws_bytes, const psvt_config *cfg, void *stream) {
+    return svt_like(PSVT_OP_SVT, A, m, n, lda, tau, Y, ldy, ws, ws_bytes, cfg, stream, false);
+}
+
+// Workspace of svt on an m x n input without the side-stream fork; 0 on a
+// bad config (the message is set).
+int svt_workspace_unforked(int64_t m, int64_t n, const psvt_config *cfg, size_t *bytes) {
+    Cfg c;
+    int rc = read_cfg(cfg, c);
+    if (rc) return rc;
+    *bytes = (m > 0 && n > 0) ? make_layout(PSVT_OP_SVT, m, n, c, false).total : 0;
+    return PSVT_OK;
+}
 
 // Stage list of one batch item or served request (records, launches
 // nothing).  ws == NULL: only report the workspace size.  chains != NULL (a

@@ -145,6 +145,18 @@ def test_config_struct_layout():
     assert got == [ctypes.sizeof(C), C.flags.offset, C.norm_safety.offset, C.status.offset, C.status_tol.offset]
 
 
+def test_noalloc_rejects_sizes_beyond_its_scratch():
+    """psvt_svt_noalloc refuses, before touching the device, a problem whose
+    workspace exceeds the static scratch (4096^2 needs ~0.9 GB)."""
+    lib = psvt.load()
+    rc = lib.psvt_svt_noalloc(FAKE, 4096, 4096, 4096, 0.5, ctypes.c_void_p(1 << 41), 4096, None, None)
+    assert rc == psvt.PSVT_EWORKSPACE
+    assert b"PSVT_NOALLOC_SCRATCH_BYTES" in lib.psvt_last_error()
+    cfg, _ = psvt.make_config(iters=300)
+    assert lib.psvt_svt_noalloc(FAKE, 8, 4, 4, 0.5, FAKE, 4, ctypes.byref(cfg), None) == psvt.PSVT_EINVAL
+    assert lib.psvt_svt_noalloc(None, 0, 4, 4, 0.5, None, 4, None, None) == psvt.PSVT_OK
+
+
 def test_empty_is_noop():
     # m == 0 returns before any pointer is used
     assert call_svt(m=0, A=None, Y=None, ws=None) == psvt.PSVT_OK
