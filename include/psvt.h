@@ -113,6 +113,7 @@ enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R
 #define PSVT_STATUS_NONFINITE_INPUT 0x1u
 #define PSVT_STATUS_NONFINITE_OUTPUT 0x2u
 #define PSVT_STATUS_NOT_CONVERGED 0x4u
+#define PSVT_STATUS_INVALID 0x8u /* batched: descriptor rejected on the device, matrix skipped */
 
 /* side selection (Proposition 1 and its footnote) */
 enum { PSVT_SIDE_AUTO = 0, PSVT_SIDE_RIGHT = 1, PSVT_SIDE_LEFT = 2 };
@@ -193,7 +194,49 @@ int psvt_svt_noalloc(const float *A, int64_t m, int64_t n, int64_t lda, double t
 int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy, void *ws,
                 size_t ws_bytes, const psvt_config *cfg, void *stream);
 
-/* Batched form: many svt (or rank_r) problems of uneven shapes.
+/* Batched form on a DEVICE array of descriptors: many svt (or rank_r)
+ * problems of uneven shapes in one call that never reads the descriptors on
+ * the host (the listing's batch note, section 4: leading batch dimensions;
+ * here uneven shapes).  Nothing is allocated, nothing is synchronised and
+ * nothing is read back: a setup kernel reads the descriptors, checks each
+ * against the maximum shape, lays out its workspace inside `ws` and picks
+ * its tile configurations with the library's cost model; then one launch
+ * per stage of the method (products: one per tile configuration) processes
+ * every matrix, each tile computed exactly as in a single call (results are
+ * bitwise psvt_svt's / psvt_rank_r's).  The call may be captured into a HIP
+ * graph and replayed; descriptors and inputs are read at run time, so their
+ * contents may change between replays.
+ *   d_descs  device array of `count` descriptors (0 <= count <= 2^20); each
+ *            needs 1 <= m <= max_m, 1 <= n <= max_n, lda >= n, ldy >= n,
+ *            non-NULL A and Y, tau finite and >= 0.  A descriptor that fails
+ *            this is skipped (Y untouched); with PSVT_FLAG_STATUS its status
+ *            word reads PSVT_STATUS_INVALID.
+ *   status   per descriptor (device pointer or NULL): with PSVT_FLAG_STATUS
+ *            in cfg the matrix's status word (psvt_config.status is not
+ *            used); ignored otherwise.
+ *   ws       device memory of psvt_batched_workspace_bytes(op, count,
+ *            max_m, max_n, cfg) bytes (a bound over every shape within the
+ *            maxima), 256-byte aligned, owned by the caller; calls that
+ *            overlap in time must not share it.
+ *   Errors are host-side checks of count, maxima, workspace and cfg (nothing
+ *   is launched then).  Outputs must not overlap inputs, other outputs or
+ *   ws (not checked: the shapes are on the device). */
+typedef struct psvt_desc {
+    const float *A; /* m x n input, row-major, device */
+    float *Y;       /* m x n output, row-major, device */
+    int64_t m, n, lda, ldy;
+    double tau;
+    uint32_t *status;
+} psvt_desc;
+int psvt_batched_workspace_bytes(int op, int32_t count, int64_t max_m, int64_t max_n, const psvt_config *cfg,
+                                 size_t *bytes);
+int psvt_svt_batched(const psvt_desc *d_descs, int32_t count, int64_t max_m, int64_t max_n, void *ws,
+                     size_t ws_bytes, const psvt_config *cfg, void *stream);
+int psvt_rank_r_batched(const psvt_desc *d_descs, int32_t count, int64_t max_m, int64_t max_n, void *ws,
+                        size_t ws_bytes, const psvt_config *cfg, void *stream);
+
+/* Batched form from a HOST item array: many svt (or rank_r) problems of
+ * uneven shapes, planned once on the host.
  *
  * psvt_batch_create plans the batch on the host: every item runs the same
  * stage list, and stage k of all items becomes grouped launches (products

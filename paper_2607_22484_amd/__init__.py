@@ -27,12 +27,13 @@ OP_SVT, OP_POLAR, OP_POLAR_SYM, OP_RANK_R = 0, 1, 2, 3
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 DTYPE_F32, DTYPE_BF16, DTYPE_FP8, DTYPE_BF16X3 = 0, 1, 2, 3
 FLAG_PLAIN_S, FLAG_SPLIT_P, FLAG_PLAIN_P, FLAG_STATUS = 0x1, 0x2, 0x4, 0x8
-STATUS_NONFINITE_INPUT, STATUS_NONFINITE_OUTPUT, STATUS_NOT_CONVERGED = 0x1, 0x2, 0x4
+STATUS_NONFINITE_INPUT, STATUS_NONFINITE_OUTPUT, STATUS_NOT_CONVERGED, STATUS_INVALID = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [
     "psvt_workspace_bytes", "psvt_svt", "psvt_svt_noalloc", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
     "psvt_strerror", "psvt_last_error", "psvt_version", "psvt_trace_begin", "psvt_trace_end",
     "psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick",
+    "psvt_batched_workspace_bytes", "psvt_svt_batched", "psvt_rank_r_batched",
     "psvt_batch_workspace_bytes", "psvt_batch_create", "psvt_batch_run", "psvt_batch_run_graph", "psvt_batch_stats",
     "psvt_batch_destroy", "psvt_server_create", "psvt_server_submit", "psvt_server_poll", "psvt_server_wait",
     "psvt_server_drain", "psvt_server_stats", "psvt_server_destroy",
@@ -70,6 +71,13 @@ class BatchItem(ctypes.Structure):
     """Mirror of ``psvt_batch_item``."""
     _fields_ = [("A", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
                 ("lda", ctypes.c_int64), ("ldy", ctypes.c_int64), ("tau", ctypes.c_double)]
+
+
+class Desc(ctypes.Structure):
+    """Mirror of ``psvt_desc`` (one matrix of a device-described batch)."""
+    _fields_ = [("A", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("ldy", ctypes.c_int64), ("tau", ctypes.c_double),
+                ("status", ctypes.c_void_p)]
 
 
 class ServerCounters(ctypes.Structure):
@@ -134,6 +142,12 @@ def load(path: Optional[str] = None):
     lib.psvt_batch_destroy.argtypes = [vp]
     for f in ("psvt_batch_workspace_bytes", "psvt_batch_create", "psvt_batch_run", "psvt_batch_run_graph",
               "psvt_batch_stats", "psvt_batch_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.psvt_batched_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int32, i64, i64, cfgp,
+                                                 ctypes.POINTER(ctypes.c_size_t)]
+    for f in ("psvt_svt_batched", "psvt_rank_r_batched"):
+        getattr(lib, f).argtypes = [vp, ctypes.c_int32, i64, i64, vp, ctypes.c_size_t, cfgp, vp]
+    for f in ("psvt_batched_workspace_bytes", "psvt_svt_batched", "psvt_rank_r_batched"):
         getattr(lib, f).restype = ctypes.c_int
     srv = ctypes.c_void_p
     lib.psvt_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, cfgp, ctypes.c_uint32,
@@ -417,6 +431,69 @@ def convert(X, dtype: int, scale: float = 1.0, transpose: bool = False, out=None
         _check(load().psvt_convert(int(dtype), X.data_ptr(), rows, cols, _ld(X), Y.data_ptr(), _ld_any(Y),
                                    float(scale), 1 if transpose else 0, _stream_ptr(X)), "psvt_convert")
     return Y
+
+
+def batched_workspace_bytes(count: int, max_m: int, max_n: int, cfg: Optional[Config] = None,
+                            op: int = OP_SVT) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().psvt_batched_workspace_bytes(op, count, max_m, max_n, ctypes.byref(cfg) if cfg is not None else None,
+                                               ctypes.byref(out)), "psvt_batched_workspace_bytes")
+    return int(out.value)
+
+
+def device_descriptors(As, taus, Ys, statuses=None, device=None):
+    """A device array (uint8 tensor) of psvt_desc for the given tensors (the
+    binding builds it on the host and copies it once)."""
+    torch = _torch()
+    arr = (Desc * len(As))()
+    for i, (A, tau, Y) in enumerate(zip(As, taus, Ys)):
+        st = statuses[i] if statuses is not None else None
+        arr[i] = Desc(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), float(tau),
+                      st.data_ptr() if st is not None else None)
+    dev = device if device is not None else As[0].device
+    return torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(dev)
+
+
+def svt_batched_raw(d_descs_ptr: int, count: int, max_m: int, max_n: int, ws, cfg: Config, op: int = OP_SVT,
+                    stream=None):
+    """psvt_svt_batched / psvt_rank_r_batched on a device descriptor array
+    (raw pointer) and a workspace tensor, on `stream` (a hipStream_t handle;
+    None = the current torch stream of ws's device)."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(ws.device).cuda_stream
+    entry = "psvt_svt_batched" if op == OP_SVT else "psvt_rank_r_batched"
+    with torch.cuda.device(ws.device):
+        _check(getattr(load(), entry)(ctypes.c_void_p(d_descs_ptr), int(count), int(max_m), int(max_n),
+                                      ws.data_ptr(), ws.numel() * ws.element_size(), ctypes.byref(cfg),
+                                      ctypes.c_void_p(stream)), entry)
+
+
+def svt_batched(As, taus, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO, flags: int = 0,
+                op: int = OP_SVT, outs=None, statuses=None, max_m=None, max_n=None):
+    """Soft-thresholding (or rank_r) of many matrices of uneven shapes in one
+    device-described batched call on the current stream; returns the
+    outputs (the descriptor array and workspace are kept until the stream
+    has passed them)."""
+    torch = _torch()
+    for A in As:
+        _check_input(A)
+    if not As:
+        return []
+    dev = As[0].device
+    Ys = list(outs) if outs is not None else [torch.empty_like(A) for A in As]
+    max_m = max_m or max(A.shape[0] for A in As)
+    max_n = max_n or max(A.shape[1] for A in As)
+    if statuses is not None:
+        flags |= FLAG_STATUS
+    cfg, keep = make_config(iters, n_fp8, n_bf16, side, None, flags)
+    need = batched_workspace_bytes(len(As), max_m, max_n, cfg, op)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    d = device_descriptors(As, taus, Ys, statuses, dev)
+    svt_batched_raw(d.data_ptr(), len(As), max_m, max_n, ws, cfg, op)
+    torch.cuda.current_stream(dev).synchronize()
+    del keep
+    return Ys
 
 
 class Batch:

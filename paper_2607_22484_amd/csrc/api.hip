@@ -33,6 +33,7 @@
 #include "../../include/psvt.h"
 #include "coeffs.h"
 #include "kernels.h"
+#include "layout.h"
 #include "plan.h"
 
 using namespace psvt;
@@ -232,27 +233,6 @@ void iteration_scales(const Cfg &c, IterScale *out) {
 
 // ---------------------------------------------------------- workspace
 
-int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
-
-struct Layout {
-    int64_t l = 0, s = 0, ldL = 0, ldS = 0;
-    bool right = true;
-    size_t scal = 0, part = 0;
-    size_t X0 = 0, X0T = 0, Xp = 0, Xq = 0, XTp = 0, XTq = 0;
-    size_t T = 0, Bm = 0;
-    size_t H = 0, R = 0, S0 = 0, S1 = 0, X2 = 0, BS = 0;
-    // low-precision operand copies: room for two bf16 planes per element
-    // (split bf16); plane strides in elements
-    bool lp = false;
-    size_t XL[2] = {0, 0}, XTL[2] = {0, 0}, TL = 0, BL = 0, SL[2] = {0, 0};
-    // S's copies of X^2 and B: the same buffers as P's unless the two
-    // iterations run concurrently (fork)
-    size_t X2L = 0, BSL = 0;
-    bool fork = false;
-    int64_t planeX = 0, planeXT = 0, planeS = 0;
-    size_t total = 0;
-};
-
 // right-sided iff n < m in auto mode (the listing's rule; square -> left)
 bool choose_right(int side, int64_t m, int64_t n) {
     if (side == PSVT_SIDE_RIGHT) return true;
@@ -260,89 +240,27 @@ bool choose_right(int side, int64_t m, int64_t n) {
     return n < m;
 }
 
-// P and S are independent once the Gram and the shifted Gram exist.  When a
-// single call's products are too small to fill the device (s <= 2048), the P
-// iterations run on a side stream, forked from and joined back into the
-// caller's stream before the final product; the layout then gives S its own
-// low-precision copies of X^2 and B.
-constexpr int64_t kForkMaxS = 2048;
-
-// single: a stand-alone call on its own stream (not a batch item or a served
-// request, whose stages are recorded and replayed in one stream)
+// Layout of op on an m x n input (layout.h).  single: a stand-alone call on
+// its own stream, which may fork P's iterations to a side stream (not a
+// batch item or a served request, whose stages are recorded and replayed in
+// one stream).
 Layout make_layout(int op, int64_t m, int64_t n, const Cfg &c, bool single = false) {
-    Layout L;
+    bool right;
+    int64_t l, s;
     if (op == PSVT_OP_POLAR_SYM) {
-        L.right = true;
-        L.l = L.s = n;
+        right = true;
+        l = s = n;
     } else if (op == PSVT_OP_POLAR) {
         // polar(A^T) = polar(A)^T: iterate on the tall orientation
-        L.right = c.side == PSVT_SIDE_AUTO ? (m >= n) : choose_right(c.side, m, n);
-        L.l = L.right ? m : n;
-        L.s = L.right ? n : m;
+        right = c.side == PSVT_SIDE_AUTO ? (m >= n) : choose_right(c.side, m, n);
+        l = right ? m : n;
+        s = right ? n : m;
     } else {
-        L.right = choose_right(c.side, m, n);
-        L.l = L.right ? m : n;
-        L.s = L.right ? n : m;
+        right = choose_right(c.side, m, n);
+        l = right ? m : n;
+        s = right ? n : m;
     }
-    L.ldL = round_up(L.l, 64);
-    L.ldS = round_up(L.s, 64);
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off += (size_t)round_up((int64_t)bytes, 256);
-        return o;
-    };
-    const size_t fS = sizeof(float) * (size_t)L.s * L.ldS;  // s x s
-    const size_t fX = sizeof(float) * (size_t)L.l * L.ldS;  // l x s
-    const size_t fXT = sizeof(float) * (size_t)L.s * L.ldL; // s x l
-    L.scal = take(sizeof(Scalars));
-    L.part = take(sizeof(double) * NORM_PARTIALS);
-    const bool need_P = op == PSVT_OP_SVT || op == PSVT_OP_POLAR;
-    const bool need_S = op != PSVT_OP_POLAR;
-    if (op != PSVT_OP_POLAR_SYM) {
-        L.X0 = take(fX);
-        L.X0T = take(fXT);
-        L.T = take(fS);
-    }
-    if (need_P) {
-        L.Xp = take(fX);
-        L.Xq = take(fX);
-        L.XTp = take(fXT);
-        L.XTq = take(fXT);
-        L.Bm = take(fS);
-    }
-    if (need_S) {
-        L.H = take(fS);
-        L.R = take(fS);
-        L.S0 = take(fS);
-        L.S1 = take(fS);
-        L.X2 = take(fS);
-        L.BS = take(fS);
-    }
-    L.lp = c.n_fp8 + c.n_bf16 > 0;
-    if (L.lp) {
-        L.TL = take(fS);
-        L.BL = take(fS);
-        L.X2L = L.TL;
-        L.BSL = L.BL;
-        if (need_P)
-            for (int i = 0; i < 2; ++i) {
-                L.XL[i] = take(fX);
-                L.XTL[i] = take(fXT);
-            }
-        if (need_S)
-            for (int i = 0; i < 2; ++i) L.SL[i] = take(fS);
-        L.planeX = L.l * L.ldS;
-        L.planeXT = L.s * L.ldL;
-        L.planeS = L.s * L.ldS;
-    }
-    L.fork = single && op == PSVT_OP_SVT && L.s <= kForkMaxS;
-    if (L.fork && L.lp) {
-        L.X2L = take(fS);
-        L.BSL = take(fS);
-    }
-    L.total = off;
-    return L;
+    return layout_for(op, l, s, right, c.n_fp8 + c.n_bf16 > 0, single);
 }
 
 // ------------------------------------------------------------ checks
@@ -390,7 +308,7 @@ hipError_t syrk(const float *A, const float *B, int64_t ld, const float *D, floa
     g.B = B;
     g.lda = g.ldb = ld;
     g.D = D;
-    g.ldd = ld;
+    g.ldd = D ? ld : 0;
     g.C = C;
     g.ldc = ldc;
     g.M = g.N = (int)s;
@@ -729,7 +647,7 @@ int status_stages(const Cfg &c, const Layout &L, void *ws, Exec &ex, const float
         }
         HIP_TRY(ex.gemm(g, OP_F32, "status: S^2 - I"), "status: S^2 - I");
         NormOp op = make_norm_op(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_CONV, 0.0);
-        op.scale = (pi ? 4.0 : 1.0) / sqrt((double)L.s);
+        op.scale = pi ? 4.0 : 1.0;  // over sqrt(s): an RMS over the s eigenvalues
         HIP_TRY(ex.norm(op, "status: convergence"), "status: convergence");
         tol = c.status_tol;
     }
@@ -929,6 +847,37 @@ int plan_request(int op, const psvt_batch_item &it, void *ws, const psvt_config 
     if ((rc = plan_svt_like(op, it.A, it.m, it.n, it.lda, it.tau, it.Y, it.ldy, ws, L, c, ex))) return rc;
     if (chains)
         for (int i = 0; i < 3; ++i) chains[i] = ex.chains ? ex.cut[i] : out.size();
+    return PSVT_OK;
+}
+
+// Stage list of one matrix of a device-described batch (no fork; with
+// PSVT_FLAG_STATUS the status stages write to `status`), and its layout.
+int plan_batched_matrix(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, uint32_t *status,
+                        std::vector<Stage> &out, Layout *layout) {
+    psvt_config local{};
+    if (cfg) local = *cfg;
+    if (local.flags & PSVT_FLAG_STATUS) local.status = status;
+    Cfg c;
+    int rc = read_cfg(&local, c);
+    if (rc) return rc;
+    const Layout L = make_layout(op, it.m, it.n, c, false);
+    if (layout) *layout = L;
+    if (!ws) return PSVT_OK;
+    Exec ex;
+    ex.rec = &out;
+    return plan_svt_like(op, it.A, it.m, it.n, it.lda, it.tau, it.Y, it.ldy, ws, L, c, ex);
+}
+
+// Side and low-precision layout flag of a batched call's configuration.
+int batched_cfg(const psvt_config *cfg, int *side, int *lp) {
+    psvt_config local{};
+    if (cfg) local = *cfg;
+    local.flags &= ~PSVT_FLAG_STATUS;
+    Cfg c;
+    int rc = read_cfg(&local, c);
+    if (rc) return rc;
+    *side = c.side;
+    *lp = c.n_fp8 + c.n_bf16 > 0;
     return PSVT_OK;
 }
 

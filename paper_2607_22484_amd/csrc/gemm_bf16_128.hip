@@ -1,9 +1,10 @@
-// MFMA tile kernels for bfloat16 operands, 128x128 tiles (single and grouped launches).
+// MFMA tile kernels for bfloat16 operands, 128x128 tiles (single, grouped and batched launches).
 #include "tile.h"
 
 namespace psvt {
 
 template hipError_t gemm_launch_bm<OP_BF16, 128, tile_occupancy<OP_BF16, 128>()>(const GemmArgs &, int, hipStream_t);
 template hipError_t gemm_grouped_bm<OP_BF16, 128, tile_occupancy<OP_BF16, 128>()>(const GemmArgs *, const int *, int, int, int, int, hipStream_t);
+template hipError_t gemm_batched_bm<OP_BF16, 128, tile_occupancy<OP_BF16, 128>()>(const BatchView &, const GemmStageT &, int, hipStream_t);
 
 }  // namespace psvt

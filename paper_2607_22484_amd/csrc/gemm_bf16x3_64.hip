@@ -1,9 +1,10 @@
-// MFMA tile kernels for split-bfloat16 (hi + lo plane) operands, 64x64 tiles (single and grouped launches).
+// MFMA tile kernels for split-bfloat16 (hi + lo plane) operands, 64x64 tiles (single, grouped and batched launches).
 #include "tile.h"
 
 namespace psvt {
 
 template hipError_t gemm_launch_bm<OP_BF16X3, 64, tile_occupancy<OP_BF16X3, 64>()>(const GemmArgs &, int, hipStream_t);
 template hipError_t gemm_grouped_bm<OP_BF16X3, 64, tile_occupancy<OP_BF16X3, 64>()>(const GemmArgs *, const int *, int, int, int, int, hipStream_t);
+template hipError_t gemm_batched_bm<OP_BF16X3, 64, tile_occupancy<OP_BF16X3, 64>()>(const BatchView &, const GemmStageT &, int, hipStream_t);
 
 }  // namespace psvt

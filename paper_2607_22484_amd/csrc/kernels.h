@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tilemodel.h"
+
 namespace psvt {
 
 // Indices into the per-call device scalar block (float part).
@@ -80,7 +82,7 @@ struct NormOp {
     int mode;
     double tau;
     double safety;     // NORM_THETA_*: theta is multiplied by it (>= 1)
-    double scale;      // NORM_CONV: D_CONV = scale * norm
+    double scale;      // NORM_CONV: D_CONV = scale * norm / sqrt(rows)
     uint32_t *status;  // NORM_STATUS: caller's status word (device)
     double tol;        // NORM_STATUS: convergence threshold on D_CONV (< 0: no check)
 };
@@ -140,7 +142,22 @@ hipError_t launch_gemm_grouped(const GemmArgs *args, const int *prefix, int n, i
 int gemm_pick_tile(const GemmArgs &g, int op_type);
 int gemm_tile_count(const GemmArgs &g, int tile);
 double gemm_model_us(const GemmArgs &g, int op_type, int tile);
-void gemm_prepare(GemmArgs &g, int op_type);
+// Per-product flags set from the operands: vector stores for C / CT, and
+// direct-to-LDS operand loads when there is one operand without prescale
+// (no A + A2 sum, no FP32 prologue factor), 16-byte aligned rows and planes,
+// and every byte offset a tile can form (rows up to M + 255) representable
+// in 31 bits (the ragged last k-tile takes masked register loads).
+__host__ __device__ inline void gemm_prepare(GemmArgs &g, int op_type) {
+    g.c_vec = g.C && ((uintptr_t)g.C & 15) == 0 && g.ldc % 4 == 0;
+    g.ct_vec = g.CT && ((uintptr_t)g.CT & 15) == 0 && g.ldct % 4 == 0;
+    const int64_t esz = op_type == OP_FP8 ? 1 : (op_type == OP_F32 ? 4 : 2);
+    const bool split = op_type == OP_BF16X3;
+    const bool prescaled = op_type == OP_F32 && (g.wa != 1.0f || g.i_wa >= 0);
+    g.direct = !g.A2 && !prescaled && g.K > 0 && ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0 &&
+               (g.lda * esz) % 16 == 0 && (g.ldb * esz) % 16 == 0 && (g.M + 256) * g.lda * esz < (1LL << 31) &&
+               (g.N + 256) * g.ldb * esz < (1LL << 31) &&
+               (!split || ((g.a_plane * esz) % 16 == 0 && (g.b_plane * esz) % 16 == 0));
+}
 // Raw launches of tile configuration `tile` (1..4 = 64/128/192/256) for
 // operand type ET (defined in tile.h, instantiated in gemm_<type>.hip); the
 // arguments must have gone through gemm_prepare.
@@ -156,7 +173,7 @@ enum NormMode {
     NORM_THETA_P = 1,  // F_P1, F_P2, F_P4 from theta = sqrt(norm)
     NORM_THETA_S = 2,  // F_S1, F_S2, F_S4
     NORM_ONLY = 3,     // D_NORM only
-    NORM_CONV = 4,     // D_CONV = scale * norm
+    NORM_CONV = 4,     // D_CONV = scale * norm / sqrt(rows)
     NORM_STATUS = 5    // norm of the output; writes the status word (below)
 };
 
@@ -164,6 +181,21 @@ enum NormMode {
 enum StatusBits { ST_NONFINITE_INPUT = 1, ST_NONFINITE_OUTPUT = 2, ST_NOT_CONVERGED = 4 };
 
 constexpr int NORM_PARTIALS = 1024;
+
+// Device-described batches (batched.h): one launch per stage (products: per
+// tile configuration), enqueue only.
+struct BatchView;
+struct GemmStageT;
+struct NormStageT;
+struct TileStageT;
+hipError_t launch_gemm_batched(const BatchView &v, const GemmStageT &st, int tile, hipStream_t stream);
+hipError_t launch_norm_batched(const BatchView &v, const NormStageT &st, int final_pass, hipStream_t stream);
+hipError_t launch_tile_batched(const BatchView &v, const TileStageT &st, hipStream_t stream);
+template <int ET>
+hipError_t gemm_launch_batched(const BatchView &v, const GemmStageT &s, int tile, hipStream_t st);
+
+// The tile cost model as the calling thread sees it (tilemodel.h).
+TileModelTable tile_model();
 
 // Tile-configuration control (autotuner and tests).
 void tune_force_tile(int c);

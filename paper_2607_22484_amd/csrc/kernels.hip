@@ -10,8 +10,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "batched.h"
 #include "device.h"
 #include "kernels.h"
+#include "tilemodel.h"
 #include "trace.h"
 
 namespace psvt {
@@ -24,62 +26,47 @@ struct TileCfg {
     const char *tag;
 };
 static const TileCfg kTiles[] = {{0, 0, ""}, {64, 4, "64"}, {128, 2, "128"}, {192, 1, "192"}, {256, 1, "256"}};
-constexpr int kNumTiles = 4;
 static const char *kTypeTag[4] = {"f32", "bf16", "fp8", "bf16x3"};
-// dense MFMA flop/s of one CU per operand type
-// (split bf16: the useful rate, a third of bf16's, since every product takes three)
-static const double kCuRate[4] = {157.3e12 / 256.0, 2516.6e12 / 256.0, 5033.2e12 / 256.0, 2516.6e12 / 3.0 / 256.0};
 
-// Cost model of one product in configuration c:  time ~= (most tiles on one
-// CU) x (overhead + tile flops / (efficiency x CU MFMA rate)), with the
-// efficiency and per-tile overhead (microseconds) per operand type, kind
-// (sym = lower-triangle product) and configuration, from the autotuner's
-// table (psvt_tune_set / psvt_tune_load).  Defaults: a measured start.
-struct TileModel {
-    float eff, overhead_us;
+// Cost model of one product in configuration c (tilemodel.h), with the
+// efficiency and per-tile overhead per operand type, kind and configuration
+// from the autotuner's table (psvt_tune_set / psvt_tune_load).  Defaults: a
+// measured start.
+static const float kDefaultEff[4][2][kNumTiles + 1] = {
+    {{0.f, 0.78f, 0.86f, 0.73f, 0.76f}, {0.f, 0.64f, 0.72f, 0.72f, 0.45f}},
+    {{0.f, 0.30f, 0.40f, 0.40f, 0.45f}, {0.f, 0.30f, 0.40f, 0.40f, 0.45f}},
+    {{0.f, 0.25f, 0.35f, 0.35f, 0.40f}, {0.f, 0.25f, 0.35f, 0.35f, 0.40f}},
+    {{0.f, 0.40f, 0.45f, 0.40f, 0.45f}, {0.f, 0.40f, 0.45f, 0.40f, 0.45f}},
 };
-static TileModel g_model[4][2][kNumTiles + 1] = {
-    {{{0.f, 0.f}, {0.78f, 19.0f}, {0.86f, 51.0f}, {0.73f, 17.0f}, {0.76f, 0.0f}},
-     {{0.f, 0.f}, {0.64f, 14.0f}, {0.72f, 20.0f}, {0.72f, 15.0f}, {0.45f, 19.0f}}},
-    {{{0.f, 0.f}, {0.30f, 6.0f}, {0.40f, 8.0f}, {0.40f, 10.0f}, {0.45f, 12.0f}},
-     {{0.f, 0.f}, {0.30f, 6.0f}, {0.40f, 8.0f}, {0.40f, 10.0f}, {0.45f, 12.0f}}},
-    {{{0.f, 0.f}, {0.25f, 6.0f}, {0.35f, 8.0f}, {0.35f, 10.0f}, {0.40f, 12.0f}},
-     {{0.f, 0.f}, {0.25f, 6.0f}, {0.35f, 8.0f}, {0.35f, 10.0f}, {0.40f, 12.0f}}},
-    {{{0.f, 0.f}, {0.40f, 8.0f}, {0.45f, 10.0f}, {0.40f, 12.0f}, {0.45f, 14.0f}},
-     {{0.f, 0.f}, {0.40f, 8.0f}, {0.45f, 10.0f}, {0.40f, 12.0f}, {0.45f, 14.0f}}},
+static const float kDefaultOverhead[4][2][kNumTiles + 1] = {
+    {{0.f, 19.0f, 51.0f, 17.0f, 0.0f}, {0.f, 14.0f, 20.0f, 15.0f, 19.0f}},
+    {{0.f, 6.0f, 8.0f, 10.0f, 12.0f}, {0.f, 6.0f, 8.0f, 10.0f, 12.0f}},
+    {{0.f, 6.0f, 8.0f, 10.0f, 12.0f}, {0.f, 6.0f, 8.0f, 10.0f, 12.0f}},
+    {{0.f, 8.0f, 10.0f, 12.0f, 14.0f}, {0.f, 8.0f, 10.0f, 12.0f, 14.0f}},
 };
+static TileModelTable make_default_table() {
+    TileModelTable t;
+    memcpy(t.eff, kDefaultEff, sizeof t.eff);
+    memcpy(t.overhead_us, kDefaultOverhead, sizeof t.overhead_us);
+    t.force = 0;
+    return t;
+}
+static TileModelTable g_table = make_default_table();
 static thread_local int g_force_tile = 0;
 
-static int tile_count(int M, int N, int sym, int bm) {
-    const int nbm = (M + bm - 1) / bm, nbn = (N + bm - 1) / bm;
-    return sym ? nbm * (nbm + 1) / 2 : nbm * nbn;
+// The model as the calling thread sees it (its forced configuration included).
+TileModelTable tile_model() {
+    TileModelTable t = g_table;
+    t.force = g_force_tile;
+    return t;
 }
 
-static double model_time_us(int type, int M, int N, int K, int sym, int c) {
-    const double bm = kTiles[c].bm;
-    const double per_cu = ceil(tile_count(M, N, sym, kTiles[c].bm) / 256.0);
-    const TileModel &tm = g_model[type][sym ? 1 : 0][c];
-    return per_cu * (tm.overhead_us + 1e6 * bm * bm * 2.0 * K / (tm.eff * kCuRate[type]));
-}
-
-static int pick_tile(int type, int M, int N, int K, int sym) {
-    if (g_force_tile >= 1 && g_force_tile <= kNumTiles) return g_force_tile;
-    double best = 1e300;
-    int arg = 2;
-    for (int c = 1; c <= kNumTiles; ++c) {
-        const double t = model_time_us(type, M, N, K, sym, c);
-        if (t < best * 0.999) {
-            best = t;
-            arg = c;
-        }
-    }
-    return arg;
-}
+static int pick_tile(int type, int M, int N, int K, int sym) { return pick_tile(tile_model(), type, M, N, K, sym); }
 
 template <int ET>
 static hipError_t launch_type(const GemmArgs &g, hipStream_t st) {
     const int tile = pick_tile(ET, g.M, g.N, g.K, g.sym);
-    const int nblocks = tile_count(g.M, g.N, g.sym, kTiles[tile].bm);
+    const int nblocks = tile_count(g.M, g.N, g.sym, tile_bm(tile));
     if (nblocks == 0) return hipSuccess;
     // useful flops: a symmetric product counts its lower triangle only
     const double flops = g.sym ? (double)g.M * (g.M + 1) * g.K : 2.0 * g.M * g.N * g.K;
@@ -109,7 +96,8 @@ int tune_set_model(int type, int c, int sym, float e, float overhead_us) {
     if (type < 0 || type > 3 || c < 1 || c > kNumTiles || (sym != 0 && sym != 1) || !(e > 0.0f && e <= 1.0f) ||
         !(overhead_us >= 0.0f && overhead_us < 1e6f))
         return -1;
-    g_model[type][sym][c] = TileModel{e, overhead_us};
+    g_table.eff[type][sym][c] = e;
+    g_table.overhead_us[type][sym][c] = overhead_us;
     return 0;
 }
 int tune_pick(int type, int M, int N, int K, int sym) { return pick_tile(type, M, N, K, sym); }
@@ -166,13 +154,13 @@ __device__ __forceinline__ void fro_final_body(const NormOp &op, double *red) {
         sc->f[base + 1] = (float)(it * it);
         sc->f[base + 2] = (float)(it * it * it * it);
     } else if (op.mode == NORM_CONV) {
-        sc->d[D_CONV] = op.scale * nrm;
+        sc->d[D_CONV] = op.scale * nrm / sqrt((double)(op.rows > 0 ? op.rows : 1));
     } else if (op.mode == NORM_STATUS) {
         uint32_t st = 0;
         if (!isfinite(sc->d[D_NU])) st |= ST_NONFINITE_INPUT;
         if (!isfinite(nrm)) st |= ST_NONFINITE_OUTPUT;
         if (op.tol >= 0.0 && !(sc->d[D_CONV] <= op.tol)) st |= ST_NOT_CONVERGED;
-        *op.status = st;
+        if (op.status) *op.status = st;
     }
 }
 
@@ -208,9 +196,37 @@ __global__ __launch_bounds__(256) void fro_final_grouped(const NormOp *ops) {
     fro_final_body(op, red);
 }
 
+// Batched forms (psvt_svt_batched): a fixed grid loops over the items of
+// every matrix (partial sums, or matrices for the final reduction), each
+// item's descriptor rebuilt from the stage template and the matrix record.
+__global__ __launch_bounds__(256) void fro_partial_batched(BatchView v, NormStageT st) {
+    __shared__ double red[256];
+    const int total = v.prefix[v.count];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = owner_of(v.prefix, v.count, t);
+        const MatInfo mi = v.mats[i];
+        NormOp op;
+        relocate_norm(st, mi, v.op, v.lp, op);
+        fro_partial_body(op, t - v.prefix[i], red);
+        __syncthreads();
+    }
+}
+__global__ __launch_bounds__(256) void fro_final_batched(BatchView v, NormStageT st) {
+    __shared__ double red[256];
+    for (int i = blockIdx.x; i < v.count; i += gridDim.x) {
+        const MatInfo mi = v.mats[i];
+        if (!mi.valid) continue;
+        NormOp op;
+        relocate_norm(st, mi, v.op, v.lp, op);
+        fro_final_body(op, red);
+        __syncthreads();
+    }
+}
+
 NormOp make_norm_op(const float *X, int64_t rows, int64_t cols, int64_t ld, double *partials, Scalars *sc, int mode,
                     double tau) {
     NormOp op;
+    memset(&op, 0, sizeof op);
     op.X = X;
     op.rows = rows;
     op.cols = cols;
@@ -320,6 +336,19 @@ __global__ __launch_bounds__(256) void tile_op_grouped(const TileOp *ops, const 
     const int p = find_group(prefix, n, blockIdx.x);
     const TileOp op = ops[p];  // in registers, not re-read from the table after stores
     tile_op_body(op, blockIdx.x - prefix[p], lds);
+}
+
+__global__ __launch_bounds__(256) void tile_op_batched(BatchView v, TileStageT st) {
+    __shared__ float lds[64][65];
+    const int total = v.prefix[v.count];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = owner_of(v.prefix, v.count, t);
+        const MatInfo mi = v.mats[i];
+        TileOp op;
+        relocate_tile(st, mi, v.op, v.lp, op);
+        tile_op_body(op, t - v.prefix[i], lds);
+        __syncthreads();
+    }
 }
 
 int tile_op_tiles(const TileOp &op) { return (int)(((op.rows + 63) / 64) * ((op.cols + 63) / 64)); }
@@ -445,6 +474,42 @@ hipError_t launch_convert(const float *X, int64_t rows, int64_t cols, int64_t ld
     return launch_tile_op(make_convert(X, rows, cols, ldx, Y, ldy, type, scale, transpose, sc, i_scale, plane), st);
 }
 
+// ----------------------------------------------------------- batched forms
+
+hipError_t launch_norm_batched(const BatchView &v, const NormStageT &st, int final_pass, hipStream_t stream) {
+    if (final_pass) {
+        TraceScope tr(stream, "fro_final_batched", 0.0, 0.0);
+        hipLaunchKernelGGL(fro_final_batched, dim3(v.count < 1024 ? (v.count > 0 ? v.count : 1) : 1024), dim3(256), 0,
+                           stream, v, st);
+    } else {
+        TraceScope tr(stream, "fro_partial_batched", 0.0, 0.0);
+        hipLaunchKernelGGL(fro_partial_batched, dim3(2048), dim3(256), 0, stream, v, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_batched(const BatchView &v, const TileStageT &st, hipStream_t stream) {
+    char name[48];
+    snprintf(name, sizeof name, "%s_batched", kTileOpName[st.t.kind]);
+    TraceScope tr(stream, trace_name(name), 0.0, 0.0);
+    hipLaunchKernelGGL(tile_op_batched, dim3(2048), dim3(256), 0, stream, v, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_batched(const BatchView &v, const GemmStageT &st, int tile, hipStream_t stream) {
+    if (st.dtype < OP_F32 || st.dtype > OP_BF16X3 || tile < 1 || tile > kNumTiles) return hipErrorInvalidValue;
+    char name[48];
+    snprintf(name, sizeof name, "%s_%s_%s_batched", st.g.sym ? "syrk" : (st.r.p[1] ? "gemm2" : "gemm"),
+             kTypeTag[st.dtype], kTiles[tile].tag);
+    TraceScope tr(stream, trace_name(name), 0.0, 0.0);
+    switch (st.dtype) {
+        case OP_F32: return gemm_launch_batched<OP_F32>(v, st, tile, stream);
+        case OP_BF16: return gemm_launch_batched<OP_BF16>(v, st, tile, stream);
+        case OP_FP8: return gemm_launch_batched<OP_FP8>(v, st, tile, stream);
+        default: return gemm_launch_batched<OP_BF16X3>(v, st, tile, stream);
+    }
+}
+
 // ----------------------------------------------------------- grouped GEMM
 
 hipError_t launch_gemm_grouped(const GemmArgs *args, const int *prefix, int n, int total, int op_type, int tile,
@@ -465,24 +530,9 @@ hipError_t launch_gemm_grouped(const GemmArgs *args, const int *prefix, int n, i
 
 // Host helpers for building grouped launches.
 int gemm_pick_tile(const GemmArgs &g, int op_type) { return pick_tile(op_type, g.M, g.N, g.K, g.sym); }
-int gemm_tile_count(const GemmArgs &g, int tile) { return tile_count(g.M, g.N, g.sym, kTiles[tile].bm); }
+int gemm_tile_count(const GemmArgs &g, int tile) { return tile_count(g.M, g.N, g.sym, tile_bm(tile)); }
 double gemm_model_us(const GemmArgs &g, int op_type, int tile) {
-    return model_time_us(op_type, g.M, g.N, g.K, g.sym, tile);
-}
-void gemm_prepare(GemmArgs &g, int op_type) {
-    g.c_vec = g.C && ((uintptr_t)g.C & 15) == 0 && g.ldc % 4 == 0;
-    g.ct_vec = g.CT && ((uintptr_t)g.CT & 15) == 0 && g.ldct % 4 == 0;
-    // direct-to-LDS operand loads: one operand without prescale (no A + A2
-    // sum, no FP32 prologue factor), 16-byte aligned rows and planes, and
-    // every byte offset a tile can form (rows up to M + 255) representable
-    // in 31 bits; the ragged last k-tile takes masked register loads
-    const int64_t esz = op_type == OP_FP8 ? 1 : (op_type == OP_F32 ? 4 : 2);
-    const bool split = op_type == OP_BF16X3;
-    const bool prescaled = op_type == OP_F32 && (g.wa != 1.0f || g.i_wa >= 0);
-    g.direct = !g.A2 && !prescaled && g.K > 0 && ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0 &&
-               (g.lda * esz) % 16 == 0 && (g.ldb * esz) % 16 == 0 && (g.M + 256) * g.lda * esz < (1LL << 31) &&
-               (g.N + 256) * g.ldb * esz < (1LL << 31) &&
-               (!split || ((g.a_plane * esz) % 16 == 0 && (g.b_plane * esz) % 16 == 0));
+    return model_time_us(tile_model(), op_type, g.M, g.N, g.K, g.sym, tile);
 }
 
 }  // namespace psvt

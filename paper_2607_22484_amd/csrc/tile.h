@@ -31,6 +31,7 @@
 
 #include <utility>
 
+#include "batched.h"
 #include "device.h"
 #include "kernels.h"
 
@@ -589,6 +590,34 @@ __global__ __launch_bounds__(256, OCC) void gemm_grouped(const GemmArgs *args, c
     gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
 }
 
+// One stage of a device-described batch (psvt_svt_batched): a fixed grid of
+// blocks loops over the stage's tiles of every matrix whose model picks this
+// configuration (the prefix sum of its count class); each tile's descriptor
+// is rebuilt from the stage template and the matrix's record, in registers.
+// The tiles are computed exactly as in a single call.
+template <int ET, int BM, int BN, int OCC, bool TWO_A, bool SYM>
+__global__ __launch_bounds__(256, OCC) void gemm_batched(BatchView v, GemmStageT st) {
+    __shared__ __attribute__((aligned(16))) uint8_t smem[TileShape<ET, BM, BN>::SMEM];
+    const int total = v.prefix[v.count];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = owner_of(v.prefix, v.count, t);
+        const MatInfo mi = v.mats[i];
+        GemmArgs g;
+        relocate_gemm(st, mi, v.op, v.lp, g);
+        int bi, bj;
+        tile_coords<SYM>(t - v.prefix[i], g.M, g.N, BM, BN, bi, bj);
+        bool done = false;
+        if constexpr (!TWO_A) {
+            if (g.direct) {
+                gemm_tile_direct<ET, BM, BN, SYM>(g, bi, bj, smem);
+                done = true;
+            }
+        }
+        if (!done) gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
+        __syncthreads();  // the next tile refills LDS
+    }
+}
+
 // ------------------------------------------------------------ launchers
 // Launchers of one tile configuration (instantiated one operand type and
 // configuration per translation unit) and the dispatchers over them.
@@ -632,6 +661,40 @@ hipError_t gemm_grouped_bm(const GemmArgs *args, const int *prefix, int n, int t
         hipLaunchKernelGGL((gemm_grouped<ET, BM, BM, OCC, false, false>), dim3(total), dim3(256), 0, st, args, prefix,
                            n);
     return hipGetLastError();
+}
+
+template <int ET, int BM, int OCC>
+hipError_t gemm_batched_bm(const BatchView &v, const GemmStageT &s, int grid, hipStream_t st) {
+    if (s.g.sym)
+        hipLaunchKernelGGL((gemm_batched<ET, BM, BM, OCC, false, true>), dim3(grid), dim3(256), 0, st, v, s);
+    else if (ET == OP_F32 && s.r.p[1] != PC_NULL)
+        hipLaunchKernelGGL((gemm_batched<ET, BM, BM, OCC, ET == OP_F32, false>), dim3(grid), dim3(256), 0, st, v, s);
+    else
+        hipLaunchKernelGGL((gemm_batched<ET, BM, BM, OCC, false, false>), dim3(grid), dim3(256), 0, st, v, s);
+    return hipGetLastError();
+}
+
+// blocks a batched stage launches for configuration `tile`: the
+// configuration's blocks per CU on every CU
+template <int ET>
+int gemm_batched_grid(int tile) {
+    switch (tile) {
+        case 1: return 256 * tile_occupancy<ET, 64>();
+        case 3: return 256;
+        case 4: return 256;
+        default: return 256 * tile_occupancy<ET, 128>();
+    }
+}
+
+template <int ET>
+hipError_t gemm_launch_batched(const BatchView &v, const GemmStageT &s, int tile, hipStream_t st) {
+    const int grid = gemm_batched_grid<ET>(tile);
+    switch (tile) {
+        case 1: return gemm_batched_bm<ET, 64, tile_occupancy<ET, 64>()>(v, s, grid, st);
+        case 3: return gemm_batched_bm<ET, 192, 1>(v, s, grid, st);
+        case 4: return gemm_batched_bm<ET, 256, 1>(v, s, grid, st);
+        default: return gemm_batched_bm<ET, 128, tile_occupancy<ET, 128>()>(v, s, grid, st);
+    }
 }
 
 template <int ET>

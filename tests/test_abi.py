@@ -234,3 +234,30 @@ def test_batch_validation():
     assert lib.psvt_batch_create(0, items, 1, None, 1 << 30, None, ctypes.byref(h)) == psvt.PSVT_EWORKSPACE
     assert lib.psvt_batch_run(None, None) == psvt.PSVT_EINVAL
     assert lib.psvt_batch_destroy(None) == psvt.PSVT_OK
+
+
+def test_batched_device_descriptors_validate():
+    """psvt_svt_batched checks count, maxima, configuration and workspace on
+    the host before any launch; its stage template relocates for every
+    schedule, side and flag set (the self-check on probe matrices runs
+    before the workspace check, so EWORKSPACE means it passed)."""
+    lib = psvt.load()
+    out = ctypes.c_size_t(0)
+    assert lib.psvt_batched_workspace_bytes(0, -1, 8, 8, None, ctypes.byref(out)) == psvt.PSVT_EINVAL
+    assert lib.psvt_batched_workspace_bytes(0, 4, 0, 8, None, ctypes.byref(out)) == psvt.PSVT_EINVAL
+    assert lib.psvt_batched_workspace_bytes(1, 4, 8, 8, None, ctypes.byref(out)) == psvt.PSVT_EINVAL  # polar
+    assert lib.psvt_batched_workspace_bytes(0, 0, 8, 8, None, ctypes.byref(out)) == psvt.PSVT_OK and out.value == 0
+    assert lib.psvt_batched_workspace_bytes(0, 3, 300, 200, None, ctypes.byref(out)) == psvt.PSVT_OK
+    assert out.value >= 3 * psvt.workspace_bytes(psvt.OP_SVT, 300, 200)
+    assert lib.psvt_svt_batched(FAKE, 0, 8, 8, None, 0, None, None) == psvt.PSVT_OK         # empty batch
+    assert lib.psvt_svt_batched(None, 2, 8, 8, FAKE, 1 << 30, None, None) == psvt.PSVT_EINVAL
+    schedules = [dict(), dict(n_bf16=18), dict(n_fp8=6, n_bf16=12), dict(n_bf16=20),
+                 dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P), dict(n_bf16=18, flags=psvt.FLAG_PLAIN_S),
+                 dict(flags=psvt.FLAG_STATUS), dict(n_bf16=18, flags=psvt.FLAG_STATUS), dict(iters=1),
+                 dict(iters=7, n_fp8=3), dict(side=psvt.SIDE_LEFT), dict(side=psvt.SIDE_RIGHT, n_bf16=4),
+                 dict(norm_safety=2.0)]
+    for kw in schedules:
+        cfg, _ = psvt.make_config(**kw)
+        for entry in (lib.psvt_svt_batched, lib.psvt_rank_r_batched):
+            rc = entry(FAKE, 2, 64, 48, FAKE, 1024, ctypes.byref(cfg), None)
+            assert rc == psvt.PSVT_EWORKSPACE, (kw, lib.psvt_last_error())
