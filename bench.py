@@ -158,6 +158,8 @@ def precision_leg(psvt, torch, dev, checks, problems=None):
         row = {}
         for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)),
                          ("bf16_plainP", dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P)),
+                         ("bf16_hform", dict(n_bf16=18, flags=psvt.FLAG_HFORM)),
+                         ("bf16_hform_plainS", dict(n_bf16=18, flags=psvt.FLAG_HFORM | psvt.FLAG_PLAIN_S)),
                          ("split_bf16_all", dict(n_bf16=20))]:
             cfg, _ = psvt.make_config(iters=20, **kw)
             ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, m, n, cfg), dtype=torch.uint8, device=dev)

@@ -80,6 +80,21 @@ enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R
  *                      the eigenvalues that decide the sign; not for
  *                      accuracy below 1e-1).
  *   PSVT_FLAG_SPLIT_P  accepted for compatibility: split P is the default.
+ *   PSVT_FLAG_HFORM    (svt only) the H-form of the sign: with P = polar(A)
+ *                      = U V^T, P^T A = V Sigma V^T, so (proof of
+ *                      Proposition 1) S = sign(P^T A - tau I) = V1 V1^T -
+ *                      V2 V2^T, the same S as sign(A^T A - tau^2 I) but on a
+ *                      spectrum linear in sigma instead of squared.  The
+ *                      iterations of S then run after P's (one more
+ *                      product, P^T A); the shift tau is applied to the
+ *                      diagonal in FP64.  Operand precision follows the
+ *                      flags above; with PSVT_FLAG_PLAIN_S (plain bf16 S,
+ *                      one MFMA pass instead of three) the H-form measures
+ *                      0.9 - 1.5e-2 with 18 bf16 iterations, against 1.2e-1
+ *                      for plain S on the squared spectrum.  S is built
+ *                      from P, whose rotation error enters it multiplied by
+ *                      sigma_max / (sigma - tau): the H-form takes no FP8
+ *                      iterations (n_fp8 > 0 is PSVT_EINVAL).
  * FP8 iterations (n_fp8) use plain e4m3 operands in P and split bf16 in S.
  * K iterations with plain operands of unit roundoff u (2^-8 bf16, 2^-4
  * e4m3) leave polar() accurate to about u kappa sqrt(K) in the relative
@@ -109,6 +124,7 @@ enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R
 #define PSVT_FLAG_SPLIT_P 0x2u
 #define PSVT_FLAG_PLAIN_P 0x4u
 #define PSVT_FLAG_STATUS 0x8u
+#define PSVT_FLAG_HFORM 0x10u
 
 #define PSVT_STATUS_NONFINITE_INPUT 0x1u
 #define PSVT_STATUS_NONFINITE_OUTPUT 0x2u

@@ -115,7 +115,7 @@ int read_cfg(const psvt_config *c, Cfg &out) {
         return fail(PSVT_EINVAL, "n_fp8 = %d, n_bf16 = %d do not fit in %d iterations", c->n_fp8, c->n_bf16,
                     out.iters);
     if (c->side < 0 || c->side > 2) return fail(PSVT_EINVAL, "side = %d", c->side);
-    const uint32_t known = PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S | PSVT_FLAG_PLAIN_P | PSVT_FLAG_STATUS;
+    const uint32_t known = PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S | PSVT_FLAG_PLAIN_P | PSVT_FLAG_STATUS | PSVT_FLAG_HFORM;
     if (c->flags & ~known) return fail(PSVT_EINVAL, "unknown flags 0x%x", c->flags);
     if ((c->flags & PSVT_FLAG_SPLIT_P) && (c->flags & PSVT_FLAG_PLAIN_P))
         return fail(PSVT_EINVAL, "PSVT_FLAG_SPLIT_P and PSVT_FLAG_PLAIN_P exclude each other");
@@ -166,7 +166,8 @@ int iter_dtype_P(const Cfg &c, int t) {
 // the eigenvalues that decide the sign sit far below bf16 resolution of the
 // largest one (sigma_min^2 - tau^2 vs sigma_max^2).  Their low-precision
 // iterations therefore use split bf16 (about 16 mantissa bits) unless
-// PSVT_FLAG_PLAIN_S asks for plain operands.
+// PSVT_FLAG_PLAIN_S asks for plain operands (with the H-form, whose S
+// spectrum is linear in sigma, plain operands come within about 1e-2).
 int iter_dtype_S(const Cfg &c, int t) {
     const int d = iter_dtype(c, t);
     if (d == OP_F32 || (c.flags & PSVT_FLAG_PLAIN_S)) return d;
@@ -384,7 +385,7 @@ void set_lp_out(GemmArgs &g, int type, void *row, int64_t ldrow, void *trans, in
 // the copies of X and B, with the FP32 X as the a-term).  Each product writes
 // the copies its consumer needs, in the consumer's type.
 int polar_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, float *user_out, int64_t ld_out,
-                     const float **out_P) {
+                     const float **out_P, const float **out_PT = nullptr) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     IterScale scl[257];
     iteration_scales(c, scl);
@@ -479,6 +480,10 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, float *u
             } else {
                 g.C = bufX[k];
                 g.ldc = L.ldS;
+                if (last && out_PT) {  // P^T too, for the H-form's P^T X0
+                    g.CT = bufXT[k];
+                    g.ldct = L.ldL;
+                }
                 if (!last) {
                     if (nd == OP_F32) {
                         g.CT = bufXT[k];
@@ -496,6 +501,7 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, float *u
         }
     }
     if (out_P) *out_P = curX;
+    if (out_PT) *out_PT = curXT;
     return PSVT_OK;
 }
 
@@ -608,6 +614,34 @@ int shifted_gram(const Layout &L, void *ws, Exec &ex, double safety) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
     double *part = (double *)at(ws, L.part);
     HIP_TRY(ex.tile(make_shift_copy(F(ws, L.T), L.s, L.ldS, F(ws, L.H), L.ldS, sc), "shift"), "shift");
+    HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, L.s, 1.0f, -1, 0.0f, -1, 0.0f, sc, ex),
+            "H^2");
+    NormOp op = make_norm_op(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_THETA_S, 0.0);
+    op.safety = safety;
+    HIP_TRY(ex.norm(op, "theta_S"), "theta_S");
+    return PSVT_OK;
+}
+
+// H-form (the proof of Proposition 1: S = V1 V1^T - V2 V2^T = sign(P^T A -
+// tau I), since P^T A = V Sigma V^T): H = P^T X0 - (tau/nu) I, R = H^2,
+// theta_S.  P^T X0 is symmetric in exact arithmetic, so it is computed as
+// a lower-triangle product (exactly symmetric) into T, free once P exists.
+int hform_shifted(const Layout &L, void *ws, const float *PT, Exec &ex, double safety) {
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    double *part = (double *)at(ws, L.part);
+    GemmArgs g = gemm_defaults();
+    g.A = PT;
+    g.B = F(ws, L.X0T);
+    g.lda = g.ldb = L.ldL;
+    g.C = F(ws, L.T);
+    g.ldc = L.ldS;
+    g.M = g.N = (int)L.s;
+    g.K = (int)L.l;
+    g.sc = sc;
+    g.sym = 1;
+    HIP_TRY(ex.gemm(g, OP_F32, "H-form: P^T X0"), "H-form: P^T X0");
+    HIP_TRY(ex.tile(make_shift_copy(F(ws, L.T), L.s, L.ldS, F(ws, L.H), L.ldS, sc, D_TAU), "H-form: shift"),
+            "H-form: shift");
     HIP_TRY(syrk(F(ws, L.H), F(ws, L.H), L.ldS, nullptr, F(ws, L.R), L.ldS, L.s, 1.0f, -1, 0.0f, -1, 0.0f, sc, ex),
             "H^2");
     NormOp op = make_norm_op(F(ws, L.R), L.s, L.s, L.ldS, part, sc, NORM_THETA_S, 0.0);
@@ -733,6 +767,23 @@ hipError_t launch_stage(const Stage &s, hipStream_t st) {
 int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
                   void *ws, const Layout &L, const Cfg &c, Exec &ex) {
     int rc;
+    if ((c.flags & PSVT_FLAG_HFORM) && op != PSVT_OP_SVT)
+        return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only (it needs the polar factor)");
+    if ((c.flags & PSVT_FLAG_HFORM) && c.n_fp8 > 0)
+        return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM takes S from P^T A: P's e4m3 iterations are too coarse for it");
+    if (c.flags & PSVT_FLAG_HFORM) {  // P first, then S from P^T A (no concurrent chains)
+        const float *P = nullptr, *PT = nullptr, *Pi = nullptr;
+        if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, true, c.safety))) return rc;
+        if ((rc = polar_iterations(c, L, ws, ex, nullptr, 0, &P, &PT))) return rc;
+        if ((rc = hform_shifted(L, ws, PT, ex, c.safety))) return rc;
+        if (ex.rec) {
+            ex.cut[0] = ex.cut[1] = ex.cut[2] = ex.rec->size();
+            ex.chains = false;
+        }
+        if ((rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi))) return rc;
+        if ((rc = final_product(L, ws, P, tau, Pi, Y, ldy, ex))) return rc;
+        return status_stages(c, L, ws, ex, Pi, L.ldS, true, Y, m, n, ldy);
+    }
     if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, op == PSVT_OP_SVT, c.safety))) return rc;
     if ((rc = shifted_gram(L, ws, ex, c.safety))) return rc;
     const float *P = nullptr, *Pi = nullptr;
@@ -923,6 +974,7 @@ int psvt_polar(const float *A, int64_t m, int64_t n, int64_t lda, float *P, int6
     Cfg c;
     int rc = read_cfg(cfg, c);
     if (rc) return rc;
+    if (c.flags & PSVT_FLAG_HFORM) return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only");
     if ((rc = check_matrix(A, m, n, lda, "A"))) return rc;
     if ((rc = check_matrix(P, m, n, ldp, "P"))) return rc;
     if (m == 0 || n == 0) return PSVT_OK;
@@ -945,6 +997,7 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
     Cfg c;
     int rc = read_cfg(cfg, c);
     if (rc) return rc;
+    if (c.flags & PSVT_FLAG_HFORM) return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only");
     if ((rc = check_matrix(G, n, n, ldg, "G"))) return rc;
     if ((rc = check_matrix(S, n, n, lds, "S"))) return rc;
     if (n == 0) return PSVT_OK;

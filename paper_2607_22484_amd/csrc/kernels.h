@@ -26,6 +26,7 @@ enum DScalarIdx {
     D_SHIFT = 1,  // (tau / nu)^2: the Gram shift in the scaled problem
     D_NORM = 2,   // last norm reduced
     D_CONV = 3,   // RMS deviation ||S^2 - I||_F / sqrt(s) of the final sign iterate
+    D_TAU = 4,    // tau / nu: the linear shift of the H-form (P^T X0 - (tau/nu) I)
     D_COUNT = 8
 };
 
@@ -104,6 +105,7 @@ struct TileOp {
     float scale;
     const Scalars *sc;
     int i_scale;
+    int i_shift;  // TOP_SHIFT: the FP64 scalar (D_*) subtracted on the diagonal
 };
 
 // Launchers (enqueue only).  Return a hipError_t.
@@ -128,7 +130,8 @@ hipError_t launch_norm_grouped(const NormOp *ops, const int *prefix, int n, int 
                                hipStream_t st);
 TileOp make_scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda, float *Y, int64_t ldy, float *YT,
                             int64_t ldyt, const Scalars *sc, int i_scale);
-TileOp make_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc);
+TileOp make_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc,
+                       int i_shift = D_SHIFT);
 TileOp make_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, int64_t ldh, const Scalars *sc);
 TileOp make_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy, int type,
                     float scale, int transpose, const Scalars *sc, int i_scale, int64_t plane);

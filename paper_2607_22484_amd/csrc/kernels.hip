@@ -143,6 +143,7 @@ __device__ __forceinline__ void fro_final_body(const NormOp &op, double *red) {
         sc->f[F_NU] = (float)nrm;
         sc->f[F_INV_NU] = nrm > 0.0 ? (float)(1.0 / nrm) : 0.0f;
         sc->d[D_SHIFT] = nrm > 0.0 ? (op.tau / nrm) * (op.tau / nrm) : 0.0;
+        sc->d[D_TAU] = nrm > 0.0 ? op.tau / nrm : 0.0;
     } else if (op.mode == NORM_THETA_P || op.mode == NORM_THETA_S) {
         // theta = sqrt(||M||_F) bounds the spectral radius of the iterate:
         // M = X^T X (or H^2) has eigenvalues mu_i >= 0 and
@@ -290,7 +291,7 @@ __device__ __forceinline__ void tile_op_body(const TileOp &op, int tile, float (
         return;
     }
     const bool need_t = (op.kind == TOP_SCALE_T && op.YT) || (op.kind == TOP_CONVERT && op.ltrans);
-    const double shift = op.kind == TOP_SHIFT ? op.sc->d[D_SHIFT] : 0.0;
+    const double shift = op.kind == TOP_SHIFT ? op.sc->d[op.i_shift] : 0.0;
     for (int k = ty; k < 64; k += 4) {
         const int64_t r = r0 + k, c = c0 + tx;
         const bool in = r < op.rows && c < op.cols;
@@ -408,8 +409,10 @@ TileOp make_scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda, f
     return op;
 }
 
-TileOp make_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc) {
+TileOp make_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc,
+                       int i_shift) {
     TileOp op = blank_op(TOP_SHIFT);
+    op.i_shift = i_shift;
     op.X = T;
     op.rows = op.cols = s;
     op.ldx = ldt;

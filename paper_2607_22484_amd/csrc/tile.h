@@ -393,8 +393,10 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uin
 // fills 8 rows per load (64 lanes x 16 bytes = 1 KB of LDS, written
 // contiguously); rows past M or N read as zero through the buffer's range
 // check.  LDS rows are 128 bytes without padding; chunk c of row r sits in
-// slot c ^ (r mod 8), so the fragment reads of 8 consecutive rows touch 8
-// different 16-byte bank groups.
+// slot c ^ ((r / 2) mod 8).  A 16-byte LDS read serves 16 lanes (256 bytes,
+// all 64 banks) per pass; the 16 lanes read 16 consecutive rows, whose
+// (row mod 2, slot) pairs are then all distinct: no bank conflict (keying
+// on r mod 8 made rows r and r + 8 collide, halving LDS throughput).
 typedef __attribute__((address_space(3))) void lds_void;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
@@ -426,7 +428,10 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
     const __amdgpu_buffer_rsrc_t ra_lo = SPLIT ? make_rsrc((const T *)g.A + g.a_plane, abytes) : ra_hi;
     const __amdgpu_buffer_rsrc_t rb_lo = SPLIT ? make_rsrc((const T *)g.B + g.b_plane, bbytes) : rb_hi;
     const int lrow = lane >> 3, lslot = lane & 7;
-    const int lchunk = lslot ^ lrow;  // global chunk this lane fetches (row % 8 == lrow)
+    // global chunk this lane fetches into slot lslot of tile row
+    // 8 (wave + 4p) + lrow: slot = chunk ^ ((row / 2) mod 8), and
+    // (row / 2) mod 8 = (4 (wave mod 2) + lrow / 2) mod 8 for every p
+    const int lchunk = lslot ^ ((4 * (wave & 1) + (lrow >> 1)) & 7);
     const int nfull = g.K / BK;                // whole k-tiles
     const int nkt = (g.K + BK - 1) / BK;       // k-tiles per segment
     const int nk = (SPLIT && !FUSED) ? 3 * nkt : nkt;
@@ -485,7 +490,9 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
         for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    const int frow = lane & 31, fh = lane >> 5, sw = frow & 7;
+    // fragment rows are 16-row aligned plus frow: the row's swizzle key
+    // is (frow / 2) mod 8
+    const int frow = lane & 31, fh = lane >> 5, sw = (frow >> 1) & 7;
     auto compute = [&](int stage) {
         const uint8_t *As = smem + stage * STAGE + (wm * (BM / 2)) * 128;
         const uint8_t *Bs = smem + stage * STAGE + BM * 128 + (wn * (BN / 2)) * 128;

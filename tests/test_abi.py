@@ -108,7 +108,7 @@ def test_config_validation():
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
     cfg, keep = psvt.make_config(iters=2, coeffs=[1.0, 0.0, float("nan"), 1, 0, 0])
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
-    cfg, _ = psvt.make_config(flags=0x10)            # unknown flag
+    cfg, _ = psvt.make_config(flags=0x20)            # unknown flag
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
     cfg, _ = psvt.make_config(flags=psvt.FLAG_SPLIT_P | psvt.FLAG_PLAIN_P)
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
@@ -120,6 +120,8 @@ def test_config_validation():
     for tol in (-1.0, float("inf")):
         cfg, _ = psvt.make_config(status=1 << 40, status_tol=tol)
         assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
+    cfg, _ = psvt.make_config(flags=psvt.FLAG_HFORM)
+    assert psvt.load().psvt_rank_r(FAKE, 8, 4, 4, 0.5, FAKE, 4, FAKE, 1 << 30, ctypes.byref(cfg), None) == psvt.PSVT_EINVAL
     # accepted settings reach the workspace check (ws = NULL here)
     for kw in (dict(flags=psvt.FLAG_PLAIN_P), dict(norm_safety=1.5), dict(status=1 << 40, status_tol=1e-4)):
         cfg, _ = psvt.make_config(**kw)
@@ -255,9 +257,13 @@ def test_batched_device_descriptors_validate():
                  dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P), dict(n_bf16=18, flags=psvt.FLAG_PLAIN_S),
                  dict(flags=psvt.FLAG_STATUS), dict(n_bf16=18, flags=psvt.FLAG_STATUS), dict(iters=1),
                  dict(iters=7, n_fp8=3), dict(side=psvt.SIDE_LEFT), dict(side=psvt.SIDE_RIGHT, n_bf16=4),
-                 dict(norm_safety=2.0)]
+                 dict(norm_safety=2.0), dict(n_bf16=18, flags=psvt.FLAG_HFORM),
+                 dict(n_bf16=12, flags=psvt.FLAG_HFORM | psvt.FLAG_STATUS)]
     for kw in schedules:
         cfg, _ = psvt.make_config(**kw)
         for entry in (lib.psvt_svt_batched, lib.psvt_rank_r_batched):
             rc = entry(FAKE, 2, 64, 48, FAKE, 1024, ctypes.byref(cfg), None)
-            assert rc == psvt.PSVT_EWORKSPACE, (kw, lib.psvt_last_error())
+            if entry is lib.psvt_rank_r_batched and kw.get("flags", 0) & psvt.FLAG_HFORM:
+                assert rc == psvt.PSVT_EINVAL   # the H-form needs the polar factor: svt only
+            else:
+                assert rc == psvt.PSVT_EWORKSPACE, (kw, lib.psvt_last_error())
