@@ -167,7 +167,33 @@ typedef struct psvt_config {
     /* Convergence threshold of PSVT_STATUS_NOT_CONVERGED on the RMS
      * deviation ||S^2 - I||_F / sqrt(s); 0 means 1e-3. */
     double status_tol;
-    int32_t reserved[4];
+    /* Warm start of the sign iteration (svt, rank_r), for a sequence of
+     * thresholdings of slowly changing inputs such as the iterates of a
+     * nuclear-norm proximal method (section 2).  pi_out (device, s x s,
+     * row stride ld_pi; NULL = not written) receives this call's
+     * Pi = (I + S)/2, s the side of the Gram matrix (n for right-sided
+     * calls, m for left-sided ones).  warm_pi (device, s x s, ld_pi;
+     * NULL = cold start) is a previous call's Pi for the same shape and
+     * side: the sign iteration then starts from
+     *     X0 = (H / theta + eps S_prev) / (1 + eps),  eps = 1e-3,
+     * H the shifted Gram, theta its spectral bound, S_prev = 2 Pi - I, and
+     * takes warm_iters (0 means 10) steps of the schedule instead of
+     * `iters` (the last two in FP32, the others in split bf16 when the
+     * schedule has low-precision iterations): every eigenvalue of X0 sits
+     * at least about eps from 0, where the cold start has to amplify
+     * eigenvalues down to |lambda| / theta.  H decides every direction with
+     * |lambda| / theta >> eps, so an error carried by S_prev is damped by
+     * about eps theta / |lambda| per call rather than accumulated; only a
+     * direction with |lambda| / theta below about eps whose sign changed
+     * since S_prev keeps the old sign, an error of at most |sigma - tau| in
+     * that direction.  P's iterations are not warm started.  warm_pi and
+     * pi_out may be the same buffer (read before written).  Not for
+     * psvt_svt_batched. */
+    const float *warm_pi;
+    float *pi_out;
+    int64_t ld_pi;
+    int32_t warm_iters;
+    int32_t reserved[3];
 } psvt_config;
 
 /* Workspace size for `op` on an m x n input (for PSVT_OP_POLAR_SYM, m = n). */
@@ -273,6 +299,11 @@ typedef struct psvt_batch_item {
     float *Y;       /* m x n output, row-major, device */
     int64_t m, n, lda, ldy;
     double tau;
+    /* per-item warm start (psvt_config.warm_pi / pi_out / ld_pi; NULL =
+     * cold / not written); the configuration's own fields are not used */
+    const float *warm_pi;
+    float *pi_out;
+    int64_t ld_pi;
 } psvt_batch_item;
 typedef struct psvt_batch psvt_batch;
 int psvt_batch_workspace_bytes(int op, const psvt_batch_item *items, int32_t count, const psvt_config *cfg,

@@ -63,14 +63,19 @@ class Config(ctypes.Structure):
         ("norm_safety", ctypes.c_double),
         ("status", ctypes.c_void_p),
         ("status_tol", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 4),
+        ("warm_pi", ctypes.c_void_p),
+        ("pi_out", ctypes.c_void_p),
+        ("ld_pi", ctypes.c_int64),
+        ("warm_iters", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
 class BatchItem(ctypes.Structure):
     """Mirror of ``psvt_batch_item``."""
     _fields_ = [("A", ctypes.c_void_p), ("Y", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
-                ("lda", ctypes.c_int64), ("ldy", ctypes.c_int64), ("tau", ctypes.c_double)]
+                ("lda", ctypes.c_int64), ("ldy", ctypes.c_int64), ("tau", ctypes.c_double),
+                ("warm_pi", ctypes.c_void_p), ("pi_out", ctypes.c_void_p), ("ld_pi", ctypes.c_int64)]
 
 
 class Desc(ctypes.Structure):
@@ -180,10 +185,11 @@ def _check(rc: int, where: str):
 
 def make_config(iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
                 coeffs: Optional[Sequence[float]] = None, flags: int = 0, norm_safety: float = 0.0,
-                status=None, status_tol: float = 0.0):
+                status=None, status_tol: float = 0.0, warm_pi=None, pi_out=None, warm_iters: int = 0):
     """A ``psvt_config``.  ``status``: a 1-element int32/uint32 GPU tensor
     (or a raw device pointer) that receives the status word; passing it sets
-    FLAG_STATUS."""
+    FLAG_STATUS.  ``warm_pi`` / ``pi_out``: s x s float32 GPU tensors (the
+    previous call's and this call's (I + S)/2; s the Gram side)."""
     cfg = Config()
     cfg.iters = int(iters)
     cfg.n_fp8 = int(n_fp8)
@@ -191,16 +197,32 @@ def make_config(iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SI
     cfg.side = int(side)
     cfg.norm_safety = float(norm_safety)
     cfg.status_tol = float(status_tol)
+    cfg.warm_iters = int(warm_iters)
     if status is not None:
         ptr = status if isinstance(status, int) else _status_ptr(status)
         cfg.status = ptr
         flags = int(flags) | FLAG_STATUS
+    ld = None
+    for t, field in ((warm_pi, "warm_pi"), (pi_out, "pi_out")):
+        if t is not None:
+            _check_pi(t)
+            setattr(cfg, field, t.data_ptr())
+            ld = _ld(t)
+    if ld is not None:
+        cfg.ld_pi = ld
     cfg.flags = int(flags)
     keep = None
     if coeffs is not None:
         keep = (ctypes.c_double * len(coeffs))(*[float(c) for c in coeffs])
         cfg.coeffs = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
     return cfg, keep
+
+
+def _check_pi(t):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.ndim != 2 or t.shape[0] != t.shape[1] or t.dtype != torch.float32 \
+            or t.device.type != "cuda" or t.stride(1) != 1:
+        raise TypeError("warm_pi / pi_out must be square float32 GPU tensors with unit column stride")
 
 
 def _status_ptr(t):
@@ -317,12 +339,15 @@ def _method(entry, op, A, tau, out, ws, kwargs, has_tau=True):
 
 def svt(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
         coeffs=None, out=None, ws=None, flags: int = 0, norm_safety: float = 0.0, status=None,
-        status_tol: float = 0.0):
+        status_tol: float = 0.0, warm_pi=None, pi_out=None, warm_iters: int = 0):
     """A_tau = U max(Sigma - tau I, 0) V^T via Proposition 1 (FP32 out).
-    ``status``: optional 1-element int32 GPU tensor for the status word."""
+    ``status``: optional 1-element int32 GPU tensor for the status word.
+    ``warm_pi`` / ``pi_out``: warm start of the sign iteration from a
+    previous call's (I + S)/2, and this call's (psvt.h)."""
     return _method("psvt_svt", OP_SVT, A, tau, out, ws,
                    dict(iters=iters, n_fp8=n_fp8, n_bf16=n_bf16, side=side, coeffs=coeffs, flags=flags,
-                        norm_safety=norm_safety, status=status, status_tol=status_tol))
+                        norm_safety=norm_safety, status=status, status_tol=status_tol, warm_pi=warm_pi,
+                        pi_out=pi_out, warm_iters=warm_iters))
 
 
 def svt_noalloc(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
@@ -348,11 +373,12 @@ def svt_noalloc(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0,
 
 def rank_r(A, tau: float, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO,
            coeffs=None, out=None, ws=None, flags: int = 0, norm_safety: float = 0.0, status=None,
-           status_tol: float = 0.0):
+           status_tol: float = 0.0, warm_pi=None, pi_out=None, warm_iters: int = 0):
     """Best rank-r approximation (Corollary 1), tau between sigma_{r+1} and sigma_r."""
     return _method("psvt_rank_r", OP_RANK_R, A, tau, out, ws,
                    dict(iters=iters, n_fp8=n_fp8, n_bf16=n_bf16, side=side, coeffs=coeffs, flags=flags,
-                        norm_safety=norm_safety, status=status, status_tol=status_tol))
+                        norm_safety=norm_safety, status=status, status_tol=status_tol, warm_pi=warm_pi,
+                        pi_out=pi_out, warm_iters=warm_iters))
 
 
 def polar(A, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO, coeffs=None, out=None,
@@ -514,7 +540,8 @@ class Batch:
         self.Ys = [torch.empty_like(A) for A in As]
         items = (BatchItem * len(As))()
         for i, (A, Y, tau) in enumerate(zip(self.As, self.Ys, taus)):
-            items[i] = BatchItem(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), float(tau))
+            items[i] = BatchItem(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), float(tau),
+                                 None, None, 0)
         self._items = items
         self.cfg, self._keep = make_config(iters, n_fp8, n_bf16, side, None, flags)
         lib = load()
@@ -575,28 +602,37 @@ class Server:
         self._pinned = {}
 
     def submit_ptr(self, A_ptr: int, Y_ptr: int, m: int, n: int, lda: int, ldy: int, tau: float,
-                   op: int = OP_SVT, stream=None) -> int:
+                   op: int = OP_SVT, stream=None, warm_pi: int = None, pi_out: int = None, ld_pi: int = 0) -> int:
         """Raw submit; ``stream``: the hipStream_t handle (int) whose pending
         work the request must follow (None = the default stream)."""
-        item = BatchItem(A_ptr, Y_ptr, m, n, lda, ldy, float(tau))
+        item = BatchItem(A_ptr, Y_ptr, m, n, lda, ldy, float(tau), warm_pi, pi_out, int(ld_pi))
         t = ctypes.c_uint64(0)
         _check(load().psvt_server_submit(self._h, op, ctypes.byref(item), ctypes.c_void_p(stream),
                                          ctypes.byref(t)), "psvt_server_submit")
         return int(t.value)
 
-    def submit(self, A, tau: float, out=None, op: int = OP_SVT):
+    def submit(self, A, tau: float, out=None, op: int = OP_SVT, warm_pi=None, pi_out=None):
         """Submit A (float32 GPU tensor); returns (ticket, Y).  The request
         is ordered after the work already queued on A's current stream (which
-        may still be producing A).  Keep A and Y alive until the ticket is
-        done."""
+        may still be producing A).  ``warm_pi`` / ``pi_out``: warm start of
+        the sign iteration from a previous request's (I + S)/2 and this
+        request's (s x s float32 GPU tensors, s the Gram side).  Keep the
+        tensors alive until the ticket is done."""
         torch = _torch()
         _check_input(A)
         Y = _output(out, tuple(A.shape), A.device)
         if A.numel() == 0:
             raise ValueError("empty request")
+        ld_pi = 0
+        for t_ in (warm_pi, pi_out):
+            if t_ is not None:
+                _check_pi(t_)
+                ld_pi = _ld(t_)
         t = self.submit_ptr(A.data_ptr(), Y.data_ptr(), A.shape[0], A.shape[1], _ld(A), _ld(Y), tau, op,
-                            stream=torch.cuda.current_stream(A.device).cuda_stream)
-        self._pinned[t] = (A, Y)
+                            stream=torch.cuda.current_stream(A.device).cuda_stream,
+                            warm_pi=warm_pi.data_ptr() if warm_pi is not None else None,
+                            pi_out=pi_out.data_ptr() if pi_out is not None else None, ld_pi=ld_pi)
+        self._pinned[t] = (A, Y, warm_pi, pi_out)
         return t, Y
 
     def poll(self, ticket: int) -> int:

@@ -97,6 +97,10 @@ struct Cfg {
     double safety;
     uint32_t *status;
     double status_tol;
+    const float *warm_pi;
+    float *pi_out;
+    int64_t ld_pi;
+    int warm_iters;
 };
 
 int read_cfg(const psvt_config *c, Cfg &out) {
@@ -108,6 +112,10 @@ int read_cfg(const psvt_config *c, Cfg &out) {
     out.safety = 1.0;
     out.status = nullptr;
     out.status_tol = 1e-3;
+    out.warm_pi = nullptr;
+    out.pi_out = nullptr;
+    out.ld_pi = 0;
+    out.warm_iters = 10;
     if (!c) return PSVT_OK;
     if (c->iters < 0 || c->iters > 256) return fail(PSVT_EINVAL, "iters = %d outside 0..256", c->iters);
     if (c->iters) out.iters = c->iters;
@@ -127,6 +135,12 @@ int read_cfg(const psvt_config *c, Cfg &out) {
         return fail(PSVT_EINVAL, "status_tol = %g must be finite and > 0", c->status_tol);
     if (c->status_tol != 0.0) out.status_tol = c->status_tol;
     if (c->flags & PSVT_FLAG_STATUS) out.status = c->status;
+    if (c->warm_iters < 0 || c->warm_iters > 64) return fail(PSVT_EINVAL, "warm_iters = %d outside 0..64", c->warm_iters);
+    if (c->warm_iters) out.warm_iters = c->warm_iters;
+    if (out.warm_iters < 2 && c->warm_pi) return fail(PSVT_EINVAL, "a warm start needs warm_iters >= 2");
+    out.warm_pi = c->warm_pi;
+    out.pi_out = c->pi_out;
+    out.ld_pi = c->ld_pi;
     out.flags = c->flags;
     out.n_fp8 = c->n_fp8;
     out.n_bf16 = c->n_bf16;
@@ -508,6 +522,17 @@ int polar_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, float *u
 // S iterations from H (s x s, ld = ldS) with R = H^2 and theta_S already in
 // the scalar block.  want_pi: the last iteration writes (I + S)/2.  Same
 // precision scheme as the P iterations, with X^2 in place of X^T X.
+//
+// Warm start (c.warm_pi, svt / rank_r): the iteration starts from
+// X0 = (H / theta_S + eps S_prev) / (1 + eps), S_prev = 2 Pi_prev - I,
+// eps = kWarmEps.  Every eigenvalue of X0 is then at least about eps away
+// from 0 unless H and S_prev disagree there, so the built-in schedule
+// (designed for eigenvalues from 1e-3 up) converges in c.warm_iters steps
+// instead of the cold start's; H decides every direction with
+// |lambda| / theta_S >> eps, so an error inherited from S_prev is damped by
+// about eps theta_S / |lambda| per call instead of carried along.
+constexpr float kWarmEps = 1e-3f;
+
 int sign_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, bool want_pi, float *user_out,
                     int64_t ld_out, const float **out_S) {
     Scalars *sc = (Scalars *)at(ws, L.scal);
@@ -520,17 +545,36 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, bool want
     float *buf[2] = {F(ws, L.S0), F(ws, L.S1)};
     void *buflp[2] = {L.lp ? at(ws, L.SL[0]) : nullptr, L.lp ? at(ws, L.SL[1]) : nullptr};
     void *X2lp = L.lp ? at(ws, L.X2L) : nullptr, *BSlp = L.lp ? at(ws, L.BSL) : nullptr;
-    for (int t = 0; t < c.iters; ++t) {
+    const bool warm = c.warm_pi && want_pi;
+    const int K = warm ? c.warm_iters : c.iters;
+    // operand type of iteration t
+    auto dtype_of = [&](int t) {
+        if (!warm) return iter_dtype_S(c, t);
+        if (t >= K - 2 || c.n_fp8 + c.n_bf16 == 0) return (int)OP_F32;
+        return (c.flags & PSVT_FLAG_PLAIN_S) ? (int)OP_BF16 : (int)OP_BF16X3;
+    };
+    if (warm) {
+        HIP_TRY(ex.tile(make_warm_start(F(ws, L.H), c.warm_pi, c.ld_pi, s, ld, buf[1], ld, sc, F_S1, kWarmEps),
+                        "S: warm start"),
+                "S: warm start");
+        cur = buf[1];
+    }
+    for (int t = 0; t < K; ++t) {
         float a, b, cc;
         coef(c, t, a, b, cc);
-        const bool first = t == 0, last = t == c.iters - 1;
-        const int dt = iter_dtype_S(c, t), nd = last ? OP_F32 : iter_dtype_S(c, t + 1);
+        const bool first = t == 0 && !warm, last = t == K - 1;
+        const int dt = dtype_of(t), nd = last ? OP_F32 : dtype_of(t + 1);
         const bool lp = dt != OP_F32;
-        const float sX = dt == OP_FP8 ? scl[t].sX : 1.0f, sT = dt == OP_FP8 ? scl[t].sT : 1.0f,
-                    sB = dt == OP_FP8 ? scl[t].sB : 1.0f, sXn = nd == OP_FP8 ? scl[t + 1].sX : 1.0f;
+        const bool fp8 = !warm && dt == OP_FP8;
+        const float sX = fp8 ? scl[t].sX : 1.0f, sT = fp8 ? scl[t].sT : 1.0f, sB = fp8 ? scl[t].sB : 1.0f,
+                    sXn = (!warm && nd == OP_FP8) ? scl[t + 1].sX : 1.0f;
         if (first && lp) {
             HIP_TRY(ex.tile(make_convert(cur, s, s, ld, buflp[1], ld, dt, sX, 0, sc, F_S1, L.planeS), "S: H copy"), "S: H copy");
             HIP_TRY(ex.tile(make_convert(R, s, s, ld, X2lp, ld, dt, sT, 0, sc, F_S2, L.planeS), "S: H^2 copy"), "S: H^2 copy");
+            curlp = buflp[1];
+        } else if (warm && t == 0 && lp) {
+            HIP_TRY(ex.tile(make_convert(cur, s, s, ld, buflp[1], ld, dt, 1.0f, 0, sc, -1, L.planeS), "S: warm copy"),
+                    "S: warm copy");
             curlp = buflp[1];
         }
         const float *sq = R;
@@ -605,6 +649,9 @@ int sign_iterations(const Cfg &c, const Layout &L, void *ws, Exec &ex, bool want
             curlp = buflp[k];
         }
     }
+    if (want_pi && c.pi_out)  // this call's Pi for the next warm start
+        HIP_TRY(ex.tile(make_scale_transpose(cur, s, s, ld, c.pi_out, c.ld_pi, nullptr, 0, nullptr, -1), "S: Pi out"),
+                "S: Pi out");
     if (out_S) *out_S = cur;
     return PSVT_OK;
 }
@@ -723,6 +770,16 @@ int final_product(const Layout &L, void *ws, const float *P, double tau, const f
     return PSVT_OK;
 }
 
+// Warm-start buffers: s x s with row stride ld_pi, outside the workspace.
+int check_warm(const Cfg &c, const Layout &L, const void *ws) {
+    if (!c.warm_pi && !c.pi_out) return PSVT_OK;
+    if (c.ld_pi < L.s) return fail(PSVT_EINVAL, "ld_pi = %lld < %lld (the Gram side)", (long long)c.ld_pi, (long long)L.s);
+    const size_t pib = span_bytes(L.s, L.s, c.ld_pi);
+    if ((c.warm_pi && overlaps(c.warm_pi, pib, ws, L.total)) || (c.pi_out && overlaps(c.pi_out, pib, ws, L.total)))
+        return fail(PSVT_EINVAL, "warm_pi / pi_out must not overlap ws");
+    return PSVT_OK;
+}
+
 int check_ws(void *ws, size_t ws_bytes, const Layout &L) {
     if (!ws) return fail(PSVT_EWORKSPACE, "workspace is NULL");
     if (ws_bytes < L.total)
@@ -767,6 +824,7 @@ hipError_t launch_stage(const Stage &s, hipStream_t st) {
 int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double tau, float *Y, int64_t ldy,
                   void *ws, const Layout &L, const Cfg &c, Exec &ex) {
     int rc;
+    if ((rc = check_warm(c, L, ws))) return rc;
     if ((c.flags & PSVT_FLAG_HFORM) && op != PSVT_OP_SVT)
         return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only (it needs the polar factor)");
     if ((c.flags & PSVT_FLAG_HFORM) && c.n_fp8 > 0)
@@ -847,6 +905,9 @@ int svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, double t
     if (overlaps(Y, span_bytes(m, n, ldy), A, span_bytes(m, n, lda)) ||
         overlaps(Y, span_bytes(m, n, ldy), ws, L.total) || overlaps(A, span_bytes(m, n, lda), ws, L.total))
         return fail(PSVT_EINVAL, "Y, A and ws must not overlap");
+    if ((rc = check_warm(c, L, ws))) return rc;
+    if ((c.flags & PSVT_FLAG_HFORM) && (op != PSVT_OP_SVT || c.n_fp8 > 0))
+        return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt without FP8 iterations");
     if ((rc = check_device())) return rc;
     Exec ex;
     ex.st = (hipStream_t)stream;
@@ -883,8 +944,13 @@ int svt_workspace_unforked(int64_t m, int64_t n, const psvt_config *cfg, size_t 
 // chain boundaries (the whole plan as one prefix when they may not).
 int plan_request(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, std::vector<Stage> &out,
                  size_t *ws_bytes, bool check_dev, size_t *chains) {
+    psvt_config local{};
+    if (cfg) local = *cfg;
+    local.warm_pi = it.warm_pi;  // per item
+    local.pi_out = it.pi_out;
+    local.ld_pi = it.ld_pi;
     Cfg c;
-    int rc = read_cfg(cfg, c);
+    int rc = read_cfg(&local, c);
     if (rc) return rc;
     if (c.status)
         return fail(PSVT_EINVAL, "PSVT_FLAG_STATUS names one status word per call: not for batch items or served "
@@ -907,6 +973,8 @@ int plan_batched_matrix(int op, const psvt_batch_item &it, void *ws, const psvt_
                         std::vector<Stage> &out, Layout *layout) {
     psvt_config local{};
     if (cfg) local = *cfg;
+    if (local.warm_pi || local.pi_out)
+        return fail(PSVT_EINVAL, "warm starts are per matrix: not in psvt_config for psvt_svt_batched");
     if (local.flags & PSVT_FLAG_STATUS) local.status = status;
     Cfg c;
     int rc = read_cfg(&local, c);
@@ -998,6 +1066,7 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
     int rc = read_cfg(cfg, c);
     if (rc) return rc;
     if (c.flags & PSVT_FLAG_HFORM) return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only");
+    if (c.warm_pi || c.pi_out) return fail(PSVT_EINVAL, "warm starts apply to svt and rank_r");
     if ((rc = check_matrix(G, n, n, ldg, "G"))) return rc;
     if ((rc = check_matrix(S, n, n, lds, "S"))) return rc;
     if (n == 0) return PSVT_OK;

@@ -89,7 +89,7 @@ struct NormOp {
 };
 
 // One 64x64-tiled elementwise pass (see kernels.hip, tile ops).
-enum TileOpKind { TOP_SCALE_T = 0, TOP_SHIFT = 1, TOP_SYMM = 2, TOP_CONVERT = 3 };
+enum TileOpKind { TOP_SCALE_T = 0, TOP_SHIFT = 1, TOP_SYMM = 2, TOP_CONVERT = 3, TOP_WARM = 4 };
 struct TileOp {
     int kind;
     const float *X;
@@ -106,6 +106,9 @@ struct TileOp {
     const Scalars *sc;
     int i_scale;
     int i_shift;  // TOP_SHIFT: the FP64 scalar (D_*) subtracted on the diagonal
+    const float *Z;  // TOP_WARM: second input (the previous (I + S)/2)
+    int64_t ldz;
+    float eps;       // TOP_WARM: weight of the previous sign
 };
 
 // Launchers (enqueue only).  Return a hipError_t.
@@ -133,6 +136,11 @@ TileOp make_scale_transpose(const float *A, int64_t m, int64_t n, int64_t lda, f
 TileOp make_shift_copy(const float *T, int64_t s, int64_t ldt, float *H, int64_t ldh, const Scalars *sc,
                        int i_shift = D_SHIFT);
 TileOp make_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, int64_t ldh, const Scalars *sc);
+// Warm start of the sign iteration: Y = (X s + eps (2 Z - I)) / (1 + eps)
+// with s = sc->f[i_scale] (Z the previous (I + S)/2, X the shifted Gram, s
+// its scale 1/theta_S).
+TileOp make_warm_start(const float *H, const float *Z, int64_t ldz, int64_t s, int64_t ldh, float *Y, int64_t ldy,
+                       const Scalars *sc, int i_scale, float eps);
 TileOp make_convert(const float *X, int64_t rows, int64_t cols, int64_t ld, void *Y, int64_t ldy, int type,
                     float scale, int transpose, const Scalars *sc, int i_scale, int64_t plane);
 hipError_t launch_tile_op(const TileOp &op, hipStream_t st);

@@ -290,6 +290,16 @@ __device__ __forceinline__ void tile_op_body(const TileOp &op, int tile, float (
         }
         return;
     }
+    if (op.kind == TOP_WARM) {
+        for (int k = ty; k < 64; k += 4) {
+            const int64_t r = r0 + k, c = c0 + tx;
+            if (r < op.rows && c < op.cols)
+                op.Y[r * op.ldy + c] =
+                    (s * op.X[r * op.ldx + c] + op.eps * (2.0f * op.Z[r * op.ldz + c] - (r == c ? 1.0f : 0.0f))) /
+                    (1.0f + op.eps);
+        }
+        return;
+    }
     const bool need_t = (op.kind == TOP_SCALE_T && op.YT) || (op.kind == TOP_CONVERT && op.ltrans);
     const double shift = op.kind == TOP_SHIFT ? op.sc->d[op.i_shift] : 0.0;
     for (int k = ty; k < 64; k += 4) {
@@ -360,11 +370,12 @@ double tile_op_bytes(const TileOp &op) {
         case TOP_SCALE_T: return e * 4.0 * (1 + (op.Y != nullptr) + (op.YT != nullptr));
         case TOP_SHIFT: return e * 8.0;
         case TOP_SYMM: return e * 12.0;
+        case TOP_WARM: return e * 12.0;
         default: return e * (4.0 + (op.ltype == OP_F32 ? 4 : op.ltype == OP_FP8 ? 1 : op.ltype == OP_BF16 ? 2 : 4));
     }
 }
 
-static const char *kTileOpName[4] = {"scale_transpose", "shift_copy", "symmetrize_scale", "convert"};
+static const char *kTileOpName[5] = {"scale_transpose", "shift_copy", "symmetrize_scale", "convert", "warm_start"};
 
 hipError_t launch_tile_op(const TileOp &op, hipStream_t st) {
     const int n = tile_op_tiles(op);
@@ -431,6 +442,22 @@ TileOp make_symmetrize_scale(const float *G, int64_t n, int64_t ldg, float *H, i
     op.ldy = ldh;
     op.sc = sc;
     op.i_scale = F_INV_NU;
+    return op;
+}
+
+TileOp make_warm_start(const float *H, const float *Z, int64_t ldz, int64_t s, int64_t ldh, float *Y, int64_t ldy,
+                       const Scalars *sc, int i_scale, float eps) {
+    TileOp op = blank_op(TOP_WARM);
+    op.eps = eps;
+    op.X = H;
+    op.ldx = ldh;
+    op.Z = Z;
+    op.ldz = ldz;
+    op.rows = op.cols = s;
+    op.Y = Y;
+    op.ldy = ldy;
+    op.sc = sc;
+    op.i_scale = i_scale;
     return op;
 }
 

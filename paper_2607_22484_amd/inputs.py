@@ -204,3 +204,34 @@ def serve_shapes(count: int, idx: int = 0, lo: int = 256, hi: int = 4096):
         r = int(min(rng.choice([16, 64, 256]), min(m, n) // 4))
         out.append((m, n, max(r, 1)))
     return out
+
+
+CFG_COMPLETION = 10  # matrix-completion problems for the proximal client
+
+
+@dataclasses.dataclass
+class CompletionProblem:
+    """A matrix-completion problem: a rank-r matrix M (m x n, Haar factors,
+    singular values uniform in [1, 10]) observed on a random subset of its
+    entries (each kept with probability p); lam the nuclear-norm weight."""
+    M: np.ndarray
+    mask: np.ndarray
+    lam: float
+    rank: int
+    name: str = ""
+
+
+def completion_problem(m: int, n: int, rank: int, p: float = 0.5, idx: int = 0, lam_rel: float = 0.05,
+                       cfg: int = CFG_COMPLETION) -> CompletionProblem:
+    """M = U diag(sigma) V^T (float32), mask ~ Bernoulli(p); lam = lam_rel x
+    p x sigma_max, so the threshold keeps the observed signal's directions
+    (sampling scales them by about p) and removes most of the sampling
+    noise."""
+    rng = rng_for(cfg, idx)
+    U = haar_columns(rng, m, rank)
+    V = haar_columns(rng, n, rank)
+    sig = np.sort(rng.uniform(1.0, 10.0, size=rank))[::-1]
+    M = ((U * sig) @ V.T).astype(np.float32)
+    mask = (rng.uniform(size=(m, n)) < p).astype(np.float32)
+    return CompletionProblem(M=M, mask=mask, lam=float(lam_rel * p * sig[0]), rank=rank,
+                             name="completion_%dx%d_r%d" % (m, n, rank))

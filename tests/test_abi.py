@@ -122,6 +122,19 @@ def test_config_validation():
         assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
     cfg, _ = psvt.make_config(flags=psvt.FLAG_HFORM)
     assert psvt.load().psvt_rank_r(FAKE, 8, 4, 4, 0.5, FAKE, 4, FAKE, 1 << 30, ctypes.byref(cfg), None) == psvt.PSVT_EINVAL
+    lib = psvt.load()
+    apart = dict(A=ctypes.c_void_p(1 << 43), Y=ctypes.c_void_p(1 << 41))  # A, Y and ws apart
+    cfg, _ = psvt.make_config(warm_iters=65)
+    assert call_svt(cfg=cfg, **apart) == psvt.PSVT_EINVAL and b"warm_iters" in lib.psvt_last_error()
+    cfg, _ = psvt.make_config()
+    cfg.warm_pi, cfg.ld_pi = 1 << 42, 2       # ld_pi below the Gram side (4)
+    assert call_svt(cfg=cfg, **apart) == psvt.PSVT_EINVAL and b"ld_pi" in lib.psvt_last_error()
+    cfg.warm_pi, cfg.ld_pi = (1 << 40) + 256, 4  # inside ws
+    assert call_svt(cfg=cfg, **apart) == psvt.PSVT_EINVAL and b"overlap ws" in lib.psvt_last_error()
+    cfg.warm_pi, cfg.ld_pi, cfg.warm_iters = 1 << 42, 4, 1   # a warm start needs at least 2 steps
+    assert call_svt(cfg=cfg, **apart) == psvt.PSVT_EINVAL and b"warm_iters" in lib.psvt_last_error()
+    cfg, _ = psvt.make_config(n_fp8=2, flags=psvt.FLAG_HFORM)
+    assert call_svt(cfg=cfg, **apart) == psvt.PSVT_EINVAL and b"HFORM" in lib.psvt_last_error()
     # accepted settings reach the workspace check (ws = NULL here)
     for kw in (dict(flags=psvt.FLAG_PLAIN_P), dict(norm_safety=1.5), dict(status=1 << 40, status_tol=1e-4)):
         cfg, _ = psvt.make_config(**kw)
@@ -133,9 +146,13 @@ def test_config_struct_layout():
     C compiler lays them out)."""
     import subprocess
     import tempfile
-    src = (b'#include <stddef.h>\n#include <stdio.h>\n#include "psvt.h"\nint main(void){printf("%zu %zu %zu %zu %zu\\n",'
+    src = (b'#include <stddef.h>\n#include <stdio.h>\n#include "psvt.h"\nint main(void){printf("%zu %zu %zu %zu %zu'
+           b' %zu %zu %zu %zu %zu %zu %zu\\n",'
            b' sizeof(psvt_config), offsetof(psvt_config, flags), offsetof(psvt_config, norm_safety),'
-           b' offsetof(psvt_config, status), offsetof(psvt_config, status_tol)); return 0;}\n')
+           b' offsetof(psvt_config, status), offsetof(psvt_config, status_tol), offsetof(psvt_config, warm_pi),'
+           b' offsetof(psvt_config, ld_pi), offsetof(psvt_config, warm_iters), sizeof(psvt_batch_item),'
+           b' offsetof(psvt_batch_item, warm_pi), offsetof(psvt_batch_item, ld_pi), sizeof(psvt_desc));'
+           b' return 0;}\n')
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "l.c")
         with open(c, "wb") as f:
@@ -143,8 +160,10 @@ def test_config_struct_layout():
         exe = os.path.join(d, "l")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         got = [int(x) for x in subprocess.check_output([exe]).split()]
-    C = psvt.Config
-    assert got == [ctypes.sizeof(C), C.flags.offset, C.norm_safety.offset, C.status.offset, C.status_tol.offset]
+    C, B = psvt.Config, psvt.BatchItem
+    assert got == [ctypes.sizeof(C), C.flags.offset, C.norm_safety.offset, C.status.offset, C.status_tol.offset,
+                   C.warm_pi.offset, C.ld_pi.offset, C.warm_iters.offset, ctypes.sizeof(B), B.warm_pi.offset,
+                   B.ld_pi.offset, ctypes.sizeof(psvt.Desc)]
 
 
 def test_noalloc_rejects_sizes_beyond_its_scratch():

@@ -1,0 +1,140 @@
+"""GPU tests of the warm-started sign iteration (psvt_config.warm_pi /
+pi_out) and of the proximal-gradient client on the serving loop:
+
+* a sequence of slowly changing inputs: each warm-started call within the
+  tolerance of the oracle, with 10 sign iterations instead of 20;
+* a singular value that crosses tau between two calls: the warm result is
+  off by at most |sigma - tau| in that direction (the bound psvt.h states);
+* the same input again: the warm start reproduces the cold result;
+* matrix completion through the server (prox.py), warm against cold: the
+  same final iterate within the tolerance, every sampled step's result
+  within 1e-2 of the oracle, the objective decreased."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_22484_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tdev(gpu_lib):
+    import torch
+    return torch, torch.device("cuda:0")
+
+
+def _host(torch, Y):
+    torch.cuda.synchronize()
+    return Y.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", [(384, 256), (256, 384)])
+@pytest.mark.parametrize("sched,tol", [(dict(), 1e-3), (dict(n_fp8=6, n_bf16=12), 1e-2)], ids=["fp32", "lowp"])
+def test_warm_sequence(gpu_lib, tdev, shape, sched, tol):
+    torch, dev = tdev
+    m, n = shape
+    pb = inputs.square_case(0.5, n=n, m=m, idx=9)
+    _announce("warm sequence %s %s" % (shape, sched))
+    s = min(m, n)
+    pi = torch.zeros((s, s), device=dev)
+    rng = np.random.default_rng(4)
+    A = pb.A.astype(np.float64)
+    E = rng.standard_normal(A.shape) * (np.linalg.norm(A) / np.sqrt(A.size))
+    for k in range(5):
+        Ak = (A + 1e-3 * k * E).astype(np.float32)
+        Ad = torch.from_numpy(Ak).to(dev)
+        warm = dict(warm_pi=pi) if k > 0 else {}
+        Y = _host(torch, gpu_lib.svt(Ad, pb.tau, iters=20, pi_out=pi, **warm, **sched))
+        err = oracle.rel_fro_err(Y, oracle.svt(Ak, pb.tau))
+        print("warm sequence %s %s step %d: %.3e" % (shape, sched, k, err))
+        assert err <= tol
+
+
+def test_warm_same_input_reproduces_cold(gpu_lib, tdev):
+    torch, dev = tdev
+    pb = inputs.small_case(idx=4)
+    _announce("warm same input")
+    A = torch.from_numpy(pb.A).to(dev)
+    pi = torch.zeros((128, 128), device=dev)
+    cold = _host(torch, gpu_lib.svt(A, pb.tau, pi_out=pi))
+    warm = _host(torch, gpu_lib.svt(A, pb.tau, warm_pi=pi, pi_out=pi))
+    assert np.linalg.norm(warm - cold) <= 1e-5 * np.linalg.norm(cold)
+
+
+def test_warm_crossing_is_bounded(gpu_lib, tdev):
+    """sigma_j = 1.03 tau in the first call and 0.97 tau in the second
+    (same singular vectors): the warm start keeps the previous sign for that
+    direction, an error of |sigma_j - tau| there; cold calls are exact."""
+    torch, dev = tdev
+    m, n = 300, 200
+    sig = inputs.log_spectrum(n, 10.0, 0.01)
+    tau = float(np.sqrt(sig[99] * sig[100]))
+    sig = inputs.gap_clamp(sig, tau, 1.2)
+    j = 60
+    rng = inputs.rng_for(inputs.CFG_TEST, 808)
+    U = inputs.haar_columns(rng, m, n)
+    V = inputs.haar_columns(rng, n, n)
+    _announce("warm crossing")
+    pi = torch.zeros((n, n), device=dev)
+    outs = []
+    for k, sj in enumerate([1.03 * tau, 0.97 * tau]):
+        s = sig.copy()
+        s[j] = sj
+        A = ((U * s) @ V.T).astype(np.float32)
+        warm = dict(warm_pi=pi) if k else {}
+        Y = _host(torch, gpu_lib.svt(torch.from_numpy(A).to(dev), tau, iters=20, pi_out=pi, **warm))
+        ref = oracle.svt(A, tau)
+        outs.append((Y, ref, sj))
+    Y, ref, sj = outs[1]
+    err = np.linalg.norm(Y - ref)
+    print("crossing: warm error %.3e, bound |sigma_j - tau| = %.3e" % (err, abs(sj - tau)))
+    assert err <= abs(sj - tau) * 1.01 + 1e-3 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("shape", [(240, 160), (160, 240)])
+def test_completion_loop_warm_vs_cold(gpu_lib, tdev, shape):
+    """Matrix completion (rank 5, half of the entries observed) through the
+    server with 18 BF16 + 2 FP32 iterations (the completion iterates carry a
+    sampling-noise bulk near tau, where e4m3 P iterations are too coarse:
+    psvt.h): warm and cold loops reach the same iterate, sampled steps match
+    the oracle, and the objective decreases."""
+    torch, dev = tdev
+    from paper_2607_22484_amd import prox
+    m, n = shape
+    pb = inputs.completion_problem(m, n, rank=5, p=0.5, idx=1)
+    _announce("completion loop %s" % (shape,))
+    M = torch.from_numpy(pb.M).to(dev)
+    mask = torch.from_numpy(pb.mask).to(dev)
+    M_obs = mask * M
+    finals = {}
+    for warm in (False, True):
+        srv = gpu_lib.Server(budget_bytes=1 << 30, max_slots=4, iters=20, n_bf16=18)
+        loop = prox.CompletionLoop(M_obs, mask, pb.lam, steps=40, warm=warm, name="w" if warm else "c")
+        obj0 = 0.5 * float(((mask * M) ** 2).sum().item())  # objective at X = 0
+        prox.solve(srv, loop, record=True)
+        srv.close()
+        finals[warm] = _host(torch, loop.X)
+        assert loop.objective() < obj0
+        worst = 0.0
+        checked = [r for r in loop.inputs if r[3]][-4:] + loop.inputs[::8]   # warm steps and a spread of steps
+        for step, G, Y, w in checked:
+            Gh = _host(torch, G)
+            worst = max(worst, oracle.rel_fro_err(_host(torch, Y), oracle.svt(Gh, loop.tau)))
+        print("completion %s warm=%s: %d of %d steps warm, worst checked step error %.3e"
+              % (shape, warm, loop.warm_steps, loop.k, worst))
+        assert worst <= 1e-2
+        if warm:
+            assert loop.warm_steps > 0
+        rec = np.linalg.norm(finals[warm] - pb.M) / np.linalg.norm(pb.M)
+        print("completion %s warm=%s: relative distance to M after 40 steps %.3e" % (shape, warm, rec))
+    diff = np.linalg.norm(finals[True] - finals[False]) / np.linalg.norm(finals[False])
+    print("completion %s: warm vs cold final iterate %.3e" % (shape, diff))
+    assert diff <= 1e-2
