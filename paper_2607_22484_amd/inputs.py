@@ -211,9 +211,10 @@ CFG_COMPLETION = 10  # matrix-completion problems for the proximal client
 
 @dataclasses.dataclass
 class CompletionProblem:
-    """A matrix-completion problem: a rank-r matrix M (m x n, Haar factors,
-    singular values uniform in [1, 10]) observed on a random subset of its
-    entries (each kept with probability p); lam the nuclear-norm weight."""
+    """A matrix-completion problem: M = rank-r signal (Haar factors, singular
+    values uniform in [1, 10]) plus small Gaussian noise, observed on a random
+    subset of its entries (each kept with probability p); lam the
+    nuclear-norm weight."""
     M: np.ndarray
     mask: np.ndarray
     lam: float
@@ -221,17 +222,42 @@ class CompletionProblem:
     name: str = ""
 
 
-def completion_problem(m: int, n: int, rank: int, p: float = 0.5, idx: int = 0, lam_rel: float = 0.05,
-                       cfg: int = CFG_COMPLETION) -> CompletionProblem:
-    """M = U diag(sigma) V^T (float32), mask ~ Bernoulli(p); lam = lam_rel x
-    p x sigma_max, so the threshold keeps the observed signal's directions
-    (sampling scales them by about p) and removes most of the sampling
-    noise."""
+def completion_lam(fro_M: float, m: int, n: int, p: float, lam_mult: float) -> float:
+    """lam = lam_mult x the sampling noise's spectral edge: observing M on a
+    Bernoulli(p) mask gives p M + E, E with independent entries of variance
+    about p (1 - p) ||M||_F^2 / (m n), so ||E||_2 is about
+    sqrt(p (1 - p)) ||M||_F / sqrt(m n) (sqrt(m) + sqrt(n)).  With lam_mult
+    = 2 the thresholding removes that bulk with a factor-2 gap and keeps the
+    signal directions above it."""
+    return lam_mult * math.sqrt(p * (1.0 - p)) * fro_M / math.sqrt(m * n) * (math.sqrt(m) + math.sqrt(n))
+
+
+def completion_problem(m: int, n: int, rank: int, p: float = 0.8, idx: int = 0, lam_mult: float = 2.0,
+                       noise: float = 0.01, cfg: int = CFG_COMPLETION) -> CompletionProblem:
+    """M = U diag(sigma) V^T + N (float32; N i.i.d. N(0, (noise/sqrt(n))^2)),
+    mask ~ Bernoulli(p), lam from ``completion_lam``."""
     rng = rng_for(cfg, idx)
     U = haar_columns(rng, m, rank)
     V = haar_columns(rng, n, rank)
     sig = np.sort(rng.uniform(1.0, 10.0, size=rank))[::-1]
-    M = ((U * sig) @ V.T).astype(np.float32)
+    M = (U * sig) @ V.T + rng.standard_normal((m, n)) * (noise / math.sqrt(n))
     mask = (rng.uniform(size=(m, n)) < p).astype(np.float32)
-    return CompletionProblem(M=M, mask=mask, lam=float(lam_rel * p * sig[0]), rank=rank,
+    lam = completion_lam(float(np.linalg.norm(M)), m, n, p, lam_mult)
+    return CompletionProblem(M=M.astype(np.float32), mask=mask, lam=lam, rank=rank,
                              name="completion_%dx%d_r%d" % (m, n, rank))
+
+
+def completion_problem_device(torch, gen, m: int, n: int, rank: int, p: float = 0.8, lam_mult: float = 2.0,
+                              noise: float = 0.01):
+    """The serving stream's matrix-completion problem (the recipe of
+    ``completion_problem``), drawn on the device from the seeded torch
+    generator ``gen`` (Haar factors from the QR of Gaussians); returns
+    (M_obs = mask * M, mask, lam)."""
+    dev = gen.device
+    U = torch.linalg.qr(torch.randn(m, rank, device=dev, generator=gen))[0]
+    V = torch.linalg.qr(torch.randn(n, rank, device=dev, generator=gen))[0]
+    sig = 1.0 + 9.0 * torch.rand(rank, device=dev, generator=gen)
+    M = (U * sig) @ V.T + torch.randn(m, n, device=dev, generator=gen) * (noise / math.sqrt(n))
+    mask = (torch.rand(m, n, device=dev, generator=gen) < p).to(torch.float32)
+    lam = completion_lam(float(M.norm().item()), m, n, p, lam_mult)
+    return (mask * M).contiguous(), mask, lam

@@ -36,26 +36,31 @@ class CompletionLoop:
     """One proximal-gradient solver whose thresholdings go to a server."""
 
     def __init__(self, M_obs, mask, lam: float, steps: int, eta: float = 1.0, warm: bool = True, name: str = "",
-                 warm_tol: float = 5e-3):
+                 warm_tol: float = 5e-3, record_steps=()):
         import torch
         self.torch = torch
         self.M_obs = M_obs            # observed entries (zeros elsewhere), device float32
         self.mask = mask              # 0/1 device float32
         self.lam, self.eta, self.steps, self.warm = float(lam), float(eta), int(steps), bool(warm)
         self.warm_tol = float(warm_tol)
-        self.warm_steps = 0
-        self.G_prev = None
         self.name = name
+        self.record_steps = set(record_steps)
         m, n = M_obs.shape
-        self.X = torch.zeros_like(M_obs)
         s = n if n < m else m        # the Gram side (right-sided iff n < m)
-        self.pi = torch.zeros((s, s), dtype=torch.float32, device=M_obs.device)
+        self.pi = torch.empty((s, s), dtype=torch.float32, device=M_obs.device)
+        self.reset()
+
+    def reset(self):
+        """Back to X = 0 at step 0 (the problem data are kept)."""
+        self.X = self.torch.zeros_like(self.M_obs)
+        self.pi.zero_()
         self.k = 0
+        self.warm_steps = 0
         self.ticket = None
-        self.G = None
-        self.Y = None
+        self.G = self.G_prev = self.Y = None
         self.t_start = None
-        self.inputs: List = []        # optional record of (step, G, Y, warm) for checks
+        # record of (step, G, Y, warm, warm_pi as submitted or None) for checks
+        self.inputs: List = []
 
     @property
     def tau(self) -> float:
@@ -78,9 +83,11 @@ class CompletionLoop:
         self.G = self.gradient_step()
         warm = self.use_warm()
         self.warm_steps += int(warm)
+        record = record or self.k in self.record_steps
+        snap = self.pi.clone() if (record and warm) else None   # the request overwrites pi
         self.ticket, self.Y = srv.submit(self.G, self.tau, warm_pi=self.pi if warm else None, pi_out=self.pi)
         if record:
-            self.inputs.append((self.k, self.G, self.Y, warm))
+            self.inputs.append((self.k, self.G, self.Y, warm, snap))
 
     def complete(self):
         self.X = self.Y
@@ -113,7 +120,9 @@ def run_loops(srv, loops: List[CompletionLoop], arrivals: np.ndarray, poll_s: fl
               record_every: int = 0) -> dict:
     """Drive ``loops`` through the server: loop i starts at ``arrivals[i]``
     seconds after the call, and each loop submits its next step as soon as
-    its previous one is done.  Returns counts and the wall time."""
+    its previous one is done (steps in a loop's ``record_steps``, or every
+    ``record_every``-th step, are recorded).  Returns counts and the wall
+    time."""
     from . import RQ_DONE, RQ_FAILED
     t0 = time.perf_counter()
     pending = sorted(range(len(loops)), key=lambda i: arrivals[i])
