@@ -125,6 +125,9 @@ enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R
 #define PSVT_FLAG_PLAIN_P 0x4u
 #define PSVT_FLAG_STATUS 0x8u
 #define PSVT_FLAG_HFORM 0x10u
+/* psvt_svt_batched / psvt_rank_r_batched only: run the batch as ONE
+ * persistent launch (below); PSVT_EINVAL elsewhere. */
+#define PSVT_FLAG_PERSISTENT 0x20u
 
 #define PSVT_STATUS_NONFINITE_INPUT 0x1u
 #define PSVT_STATUS_NONFINITE_OUTPUT 0x2u
@@ -262,7 +265,25 @@ int psvt_rank_r(const float *A, int64_t m, int64_t n, int64_t lda, double tau, f
  *            overlap in time must not share it.
  *   Errors are host-side checks of count, maxima, workspace and cfg (nothing
  *   is launched then).  Outputs must not overlap inputs, other outputs or
- *   ws (not checked: the shapes are on the device). */
+ *   ws (not checked: the shapes are on the device).
+ *
+ * PSVT_FLAG_PERSISTENT: after the setup kernels (the descriptor pass, a few
+ * small kernels that copy the stage templates into ws, and one that lays out
+ * the dependency counts), ONE launch of two blocks per CU runs every stage of
+ * every matrix.  Blocks take tickets in the order of the per-stage launches
+ * (stage by stage, matrices in order, tiles in order); an item of matrix i
+ * waits until matrix i has completed all its items of earlier stages, so
+ * small matrices run ahead of large ones and no stage drains the device.
+ * Every wait is on an item with a lower ticket, held by a running block, so
+ * the launch always drains; a wait is also bounded (about seconds,
+ * psvt_tune_spin_limit): past the bound the block raises the abort flag,
+ * every later item is skipped, the launch ends, the 32-bit word at byte 4
+ * of ws reads nonzero and, with PSVT_FLAG_STATUS, status words read
+ * PSVT_STATUS_INVALID for the matrices that did not finish.  The executor
+ * holds tiles up to 128 x 128 (f32, bf16) and 64 x 64 (split bf16, fp8):
+ * results are bitwise those of single calls made with
+ * psvt_tune_persistent_tiles(1) on the calling thread.  The workspace is
+ * larger (psvt_batched_workspace_bytes with the flag set). */
 typedef struct psvt_desc {
     const float *A; /* m x n input, row-major, device */
     float *Y;       /* m x n output, row-major, device */
@@ -276,6 +297,19 @@ int psvt_svt_batched(const psvt_desc *d_descs, int32_t count, int64_t max_m, int
                      size_t ws_bytes, const psvt_config *cfg, void *stream);
 int psvt_rank_r_batched(const psvt_desc *d_descs, int32_t count, int64_t max_m, int64_t max_n, void *ws,
                         size_t ws_bytes, const psvt_config *cfg, void *stream);
+
+/* Host-only replay of the persistent executor's schedule (for tests; no
+ * device is touched): for `count` shapes ms[i] x ns[i] (host arrays) it
+ * builds the tables the setup kernels would, checks that tickets map one to
+ * one onto items, that each item's dependency count is its matrix's items of
+ * earlier launches, and that `blocks` simulated blocks with random item
+ * durations (xorshift from `seed`) drain every ticket without deadlock, no
+ * item starting before its matrix's earlier launches completed.  *tickets =
+ * the launch's ticket count.  PSVT_EINVAL with psvt_last_error() naming the
+ * first violated check. */
+int psvt_batched_check_schedule(int op, const int64_t *ms, const int64_t *ns, int32_t count, int64_t max_m,
+                                int64_t max_n, const psvt_config *cfg, int32_t blocks, uint64_t seed,
+                                int64_t *tickets);
 
 /* Batched form from a HOST item array: many svt (or rank_r) problems of
  * uneven shapes, planned once on the host.
@@ -440,12 +474,23 @@ int psvt_trace_end(psvt_trace_stat *out, int max_entries, int *n_entries);
  *                              line, and then nothing is applied.
  *   psvt_tune_pick             the id the model picks for an M x N x K
  *                              product (>= 1), or a negative error code.
+ *   psvt_tune_persistent_tiles(on)  single calls on the calling thread pick
+ *                              from the persistent executor's tile set
+ *                              (PSVT_FLAG_PERSISTENT), so that they compute
+ *                              every tile as it does (1 = on, 0 = off).
+ *   psvt_tune_spin_limit(n)    the calling thread's bound on one dependency
+ *                              wait of the persistent executor, in polls
+ *                              (about a microsecond each; default 2^22,
+ *                              0 = abort on any wait that is not already
+ *                              satisfied: a test of the abort path).
  * The model is process-wide; change it before concurrent calls. */
 enum { PSVT_DTYPE_F32 = 0, PSVT_DTYPE_BF16 = 1, PSVT_DTYPE_FP8 = 2, PSVT_DTYPE_BF16X3 = 3 };
 int psvt_tune_force_tile(int tile);
 int psvt_tune_set(int dtype, int tile, int sym, double efficiency, double overhead_us);
 int psvt_tune_load(const char *path);
 int psvt_tune_pick(int dtype, int64_t M, int64_t N, int64_t K, int sym);
+int psvt_tune_persistent_tiles(int on);
+int psvt_tune_spin_limit(int64_t polls);
 
 /* Static description of a return code. */
 const char *psvt_strerror(int code);

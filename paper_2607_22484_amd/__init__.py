@@ -27,13 +27,14 @@ OP_SVT, OP_POLAR, OP_POLAR_SYM, OP_RANK_R = 0, 1, 2, 3
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 DTYPE_F32, DTYPE_BF16, DTYPE_FP8, DTYPE_BF16X3 = 0, 1, 2, 3
 FLAG_PLAIN_S, FLAG_SPLIT_P, FLAG_PLAIN_P, FLAG_STATUS, FLAG_HFORM = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_PERSISTENT = 0x20
 STATUS_NONFINITE_INPUT, STATUS_NONFINITE_OUTPUT, STATUS_NOT_CONVERGED, STATUS_INVALID = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [
     "psvt_workspace_bytes", "psvt_svt", "psvt_svt_noalloc", "psvt_polar", "psvt_polar_sym", "psvt_rank_r", "psvt_gemm_nt", "psvt_convert",
     "psvt_strerror", "psvt_last_error", "psvt_version", "psvt_trace_begin", "psvt_trace_end",
-    "psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick",
-    "psvt_batched_workspace_bytes", "psvt_svt_batched", "psvt_rank_r_batched",
+    "psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick", "psvt_tune_persistent_tiles",
+    "psvt_tune_spin_limit", "psvt_batched_workspace_bytes", "psvt_batched_check_schedule", "psvt_svt_batched", "psvt_rank_r_batched",
     "psvt_batch_workspace_bytes", "psvt_batch_create", "psvt_batch_run", "psvt_batch_run_graph", "psvt_batch_stats",
     "psvt_batch_destroy", "psvt_server_create", "psvt_server_submit", "psvt_server_poll", "psvt_server_wait",
     "psvt_server_drain", "psvt_server_stats", "psvt_server_destroy",
@@ -134,7 +135,10 @@ def load(path: Optional[str] = None):
     lib.psvt_tune_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     lib.psvt_tune_load.argtypes = [ctypes.c_char_p]
     lib.psvt_tune_pick.argtypes = [ctypes.c_int, i64, i64, i64, ctypes.c_int]
-    for f in ("psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick"):
+    lib.psvt_tune_persistent_tiles.argtypes = [ctypes.c_int]
+    lib.psvt_tune_spin_limit.argtypes = [i64]
+    for f in ("psvt_tune_force_tile", "psvt_tune_set", "psvt_tune_load", "psvt_tune_pick",
+              "psvt_tune_persistent_tiles", "psvt_tune_spin_limit"):
         getattr(lib, f).restype = ctypes.c_int
     items_p = ctypes.POINTER(BatchItem)
     lib.psvt_batch_workspace_bytes.argtypes = [ctypes.c_int, items_p, ctypes.c_int32, cfgp,
@@ -152,7 +156,10 @@ def load(path: Optional[str] = None):
                                                  ctypes.POINTER(ctypes.c_size_t)]
     for f in ("psvt_svt_batched", "psvt_rank_r_batched"):
         getattr(lib, f).argtypes = [vp, ctypes.c_int32, i64, i64, vp, ctypes.c_size_t, cfgp, vp]
-    for f in ("psvt_batched_workspace_bytes", "psvt_svt_batched", "psvt_rank_r_batched"):
+    i64p = ctypes.POINTER(i64)
+    lib.psvt_batched_check_schedule.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int32, i64, i64, cfgp,
+                                                ctypes.c_int32, ctypes.c_uint64, i64p]
+    for f in ("psvt_batched_workspace_bytes", "psvt_svt_batched", "psvt_rank_r_batched", "psvt_batched_check_schedule"):
         getattr(lib, f).restype = ctypes.c_int
     srv = ctypes.c_void_p
     lib.psvt_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, cfgp, ctypes.c_uint32,
@@ -495,12 +502,36 @@ def svt_batched_raw(d_descs_ptr: int, count: int, max_m: int, max_n: int, ws, cf
                                       ctypes.c_void_p(stream)), entry)
 
 
+def check_persistent_schedule(shapes, max_m: int, max_n: int, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0,
+                              flags: int = 0, op: int = OP_SVT, blocks: int = 512, seed: int = 0) -> int:
+    """Host replay of the persistent executor's schedule for ``shapes`` (list
+    of (m, n)); raises RuntimeError naming a violated check; returns the
+    ticket count (psvt_batched_check_schedule)."""
+    n = len(shapes)
+    ms = (ctypes.c_int64 * max(n, 1))(*[int(m) for m, _ in shapes])
+    ns = (ctypes.c_int64 * max(n, 1))(*[int(k) for _, k in shapes])
+    cfg, keep = make_config(iters, n_fp8, n_bf16, SIDE_AUTO, None, flags)
+    out = ctypes.c_int64(0)
+    _check(load().psvt_batched_check_schedule(op, ms, ns, n, int(max_m), int(max_n), ctypes.byref(cfg), int(blocks),
+                                              int(seed), ctypes.byref(out)), "psvt_batched_check_schedule")
+    del keep
+    return int(out.value)
+
+
+def persistent_aborted(ws) -> bool:
+    """After a PSVT_FLAG_PERSISTENT call on ``ws`` (once its stream has
+    passed it): whether a dependency wait passed its bound (the word at byte
+    4 of the workspace)."""
+    return bool(int(ws[4:8].view(_torch().int32).item()))
+
+
 def svt_batched(As, taus, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side: int = SIDE_AUTO, flags: int = 0,
-                op: int = OP_SVT, outs=None, statuses=None, max_m=None, max_n=None):
+                op: int = OP_SVT, outs=None, statuses=None, max_m=None, max_n=None, persistent: bool = False):
     """Soft-thresholding (or rank_r) of many matrices of uneven shapes in one
     device-described batched call on the current stream; returns the
     outputs (the descriptor array and workspace are kept until the stream
-    has passed them)."""
+    has passed them).  ``persistent``: one persistent launch
+    (PSVT_FLAG_PERSISTENT); raises RuntimeError if its abort flag is set."""
     torch = _torch()
     for A in As:
         _check_input(A)
@@ -512,6 +543,8 @@ def svt_batched(As, taus, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side
     max_n = max_n or max(A.shape[1] for A in As)
     if statuses is not None:
         flags |= FLAG_STATUS
+    if persistent:
+        flags |= FLAG_PERSISTENT
     cfg, keep = make_config(iters, n_fp8, n_bf16, side, None, flags)
     need = batched_workspace_bytes(len(As), max_m, max_n, cfg, op)
     ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
@@ -519,6 +552,8 @@ def svt_batched(As, taus, iters: int = 20, n_fp8: int = 0, n_bf16: int = 0, side
     svt_batched_raw(d.data_ptr(), len(As), max_m, max_n, ws, cfg, op)
     torch.cuda.current_stream(dev).synchronize()
     del keep
+    if persistent and persistent_aborted(ws):
+        raise RuntimeError("persistent batched call aborted: a dependency wait passed its bound")
     return Ys
 
 
@@ -688,6 +723,18 @@ def trace_end(max_entries: int = 64):
 def force_tile(tile: int):
     """Force a tile configuration id (0 = automatic) on this thread."""
     _check(load().psvt_tune_force_tile(int(tile)), "psvt_tune_force_tile")
+
+
+def persistent_tiles(on: bool):
+    """Single calls on this thread pick tiles as the persistent batched
+    executor does (for bitwise comparisons with it)."""
+    _check(load().psvt_tune_persistent_tiles(1 if on else 0), "psvt_tune_persistent_tiles")
+
+
+def spin_limit(polls: int):
+    """This thread's bound on one dependency wait of the persistent executor
+    (polls; 0 = abort on any wait not already satisfied)."""
+    _check(load().psvt_tune_spin_limit(int(polls)), "psvt_tune_spin_limit")
 
 
 def pick_tile(M: int, N: int, K: int, sym: bool = False, dtype: int = 0) -> int:

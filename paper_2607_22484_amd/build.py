@@ -18,7 +18,7 @@ OBJ_DIR = os.path.join(HERE, "_build")
 # they dominate the build
 _TILE_UNITS = ["gemm_%s_%d.hip" % (t, bm) for t in ("f32", "bf16x3", "bf16", "fp8") for bm in (256, 192, 128, 64)]
 SOURCES = _TILE_UNITS + ["gemm_f32.hip", "gemm_bf16x3.hip", "gemm_bf16.hip", "gemm_fp8.hip", "kernels.hip",
-                         "api.hip", "trace.hip", "batch.hip", "server.hip", "noalloc.hip", "batched.hip"]
+                         "api.hip", "trace.hip", "batch.hip", "server.hip", "noalloc.hip", "batched.hip", "persist.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 instructions are disabled: the compiler must not form

@@ -123,8 +123,12 @@ int read_cfg(const psvt_config *c, Cfg &out) {
         return fail(PSVT_EINVAL, "n_fp8 = %d, n_bf16 = %d do not fit in %d iterations", c->n_fp8, c->n_bf16,
                     out.iters);
     if (c->side < 0 || c->side > 2) return fail(PSVT_EINVAL, "side = %d", c->side);
-    const uint32_t known = PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S | PSVT_FLAG_PLAIN_P | PSVT_FLAG_STATUS | PSVT_FLAG_HFORM;
+    const uint32_t known = PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S | PSVT_FLAG_PLAIN_P | PSVT_FLAG_STATUS | PSVT_FLAG_HFORM |
+                           PSVT_FLAG_PERSISTENT;
     if (c->flags & ~known) return fail(PSVT_EINVAL, "unknown flags 0x%x", c->flags);
+    // the batched entry points take this flag off before they get here
+    if (c->flags & PSVT_FLAG_PERSISTENT)
+        return fail(PSVT_EINVAL, "PSVT_FLAG_PERSISTENT applies to psvt_svt_batched / psvt_rank_r_batched only");
     if ((c->flags & PSVT_FLAG_SPLIT_P) && (c->flags & PSVT_FLAG_PLAIN_P))
         return fail(PSVT_EINVAL, "PSVT_FLAG_SPLIT_P and PSVT_FLAG_PLAIN_P exclude each other");
     if (c->norm_safety != 0.0 && !(c->norm_safety >= 1.0 && c->norm_safety <= 16.0))
@@ -973,6 +977,7 @@ int plan_batched_matrix(int op, const psvt_batch_item &it, void *ws, const psvt_
                         std::vector<Stage> &out, Layout *layout) {
     psvt_config local{};
     if (cfg) local = *cfg;
+    local.flags &= ~PSVT_FLAG_PERSISTENT;  // how the batch runs, not how a matrix is planned
     if (local.warm_pi || local.pi_out)
         return fail(PSVT_EINVAL, "warm starts are per matrix: not in psvt_config for psvt_svt_batched");
     if (local.flags & PSVT_FLAG_STATUS) local.status = status;
@@ -988,10 +993,11 @@ int plan_batched_matrix(int op, const psvt_batch_item &it, void *ws, const psvt_
 }
 
 // Side and low-precision layout flag of a batched call's configuration.
-int batched_cfg(const psvt_config *cfg, int *side, int *lp) {
+int batched_cfg(const psvt_config *cfg, int *side, int *lp, int *persistent) {
     psvt_config local{};
     if (cfg) local = *cfg;
-    local.flags &= ~PSVT_FLAG_STATUS;
+    *persistent = (local.flags & PSVT_FLAG_PERSISTENT) != 0;
+    local.flags &= ~(PSVT_FLAG_STATUS | PSVT_FLAG_PERSISTENT);
     Cfg c;
     int rc = read_cfg(&local, c);
     if (rc) return rc;
@@ -1151,6 +1157,18 @@ int psvt_convert(int dtype, const float *X, int64_t rows, int64_t cols, int64_t 
 int psvt_tune_force_tile(int tile) {
     if (tile < 0 || tile > 4) return fail(PSVT_EINVAL, "tile id %d outside 0..4", tile);
     tune_force_tile(tile);
+    return PSVT_OK;
+}
+
+int psvt_tune_persistent_tiles(int on) {
+    if (on != 0 && on != 1) return fail(PSVT_EINVAL, "on must be 0 or 1");
+    tune_persistent_tiles(on);
+    return PSVT_OK;
+}
+
+int psvt_tune_spin_limit(int64_t polls) {
+    if (polls < 0 || polls > (1LL << 40)) return fail(PSVT_EINVAL, "spin limit %lld outside 0..2^40", (long long)polls);
+    set_persist_spin_limit(polls);
     return PSVT_OK;
 }
 

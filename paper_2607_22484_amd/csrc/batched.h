@@ -236,4 +236,83 @@ __host__ __device__ inline int class_count(const CountClass &c, const MatInfo &m
     return (int)(((d0 + 63) / 64) * ((d1 + 63) / 64));
 }
 
+// ----------------------------------------------- persistent executor
+// PSVT_FLAG_PERSISTENT runs a batch's stages in ONE launch: blocks take
+// tickets in (launch, item) order, where a launch is what the per-stage
+// form would launch (a stage, or one tile configuration of a product stage)
+// and its items are the prefix sum of its count class.  Matrix i's item of
+// launch j waits until matrix i has completed every item of launches < j;
+// those hold lower tickets, taken by running blocks, so the lowest
+// unfinished ticket can always run and the launch drains.  Waits are
+// bounded: past the bound a block raises the abort flag, every later item
+// is skipped, and the kernel still ends.
+
+// A template stage as the persistent kernel reads it.
+struct StageT {
+    int kind, dtype;
+    union {
+        GemmStageT g;
+        NormStageT n;
+        TileStageT t;
+    };
+};
+
+// One launch of the per-stage form: its stage, count class (-1: the final
+// pass of a norm, one item per matrix) and tile configuration.
+struct PLaunch {
+    int32_t stage;
+    int16_t cls;
+    int8_t tile, final_pass;
+};
+
+// At byte 0 of the workspace of a persistent call: the ticket counter and the
+// abort flag (nonzero after the call: a wait passed its bound, results and
+// status words of unfinished matrices are invalid).
+struct PersistCtl {
+    uint32_t ticket, abort;
+    uint32_t pad[62];
+};
+
+struct PersistArgs {
+    const MatInfo *mats;
+    int count, op, lp, status_on;
+    const int *prefix;  // count classes' prefix sums, count + 1 entries each
+    const PLaunch *launches;
+    int nl;
+    const StageT *stages;
+    int *lbase;  // nl + 1: first ticket of each launch
+    int *deps;   // count x nl: items of matrix i in launches < j
+    int *done;   // count: items of matrix i completed
+    PersistCtl *ctl;
+    long long spin_limit;
+};
+
+// Items of matrix i in launch L (count classes' prefix sums, count + 1 each).
+__host__ __device__ inline int persist_items(const PLaunch &L, const int *prefix, int count, int i) {
+    if (L.final_pass) return 1;
+    const int *pre = prefix + (size_t)L.cls * ((size_t)count + 1);
+    return pre[i + 1] - pre[i];
+}
+// All items of launch L.
+__host__ __device__ inline int persist_launch_items(const PLaunch &L, const int *prefix, int count) {
+    return L.final_pass ? count : prefix[(size_t)L.cls * ((size_t)count + 1) + count];
+}
+// Ticket T -> launch j, matrix i, item within the matrix's share of the launch.
+__host__ __device__ inline void persist_decode(const int *lbase, int nl, const PLaunch *launches, const int *prefix,
+                                               int count, int T, int &j, int &i, int &item) {
+    j = owner_of(lbase, nl, T);
+    const PLaunch L = launches[j];
+    const int t = T - lbase[j];
+    i = t;
+    item = 0;
+    if (!L.final_pass) {
+        const int *pre = prefix + (size_t)L.cls * ((size_t)count + 1);
+        i = owner_of(pre, count, t);
+        item = t - pre[i];
+    }
+}
+
+hipError_t launch_upload(void *dst, const void *src, size_t bytes, hipStream_t st);
+hipError_t launch_persistent(const PersistArgs &a, hipStream_t st);
+
 }  // namespace psvt

@@ -42,8 +42,11 @@ using namespace psvt;
 namespace psvt {
 int plan_batched_matrix(int op, const psvt_batch_item &it, void *ws, const psvt_config *cfg, uint32_t *status,
                         std::vector<Stage> &out, Layout *layout);
-int batched_cfg(const psvt_config *cfg, int *side, int *lp);
+int batched_cfg(const psvt_config *cfg, int *side, int *lp, int *persistent);
 int set_error(int code, const char *msg);
+
+static thread_local long long g_spin_limit = 1LL << 22;
+void set_persist_spin_limit(long long polls) { g_spin_limit = polls; }
 }  // namespace psvt
 
 namespace {
@@ -170,7 +173,7 @@ Sentinels sentinels(int k) {
 }
 
 struct Template {
-    int op, lp, side;
+    int op, lp, side, persistent;
     std::vector<int> kind, dtype;
     std::vector<GemmStageT> g;
     std::vector<NormStageT> n;
@@ -242,7 +245,7 @@ int plan_probe(int op, const MatInfo &mi, const psvt_config *cfg, std::vector<St
 // Plan the template matrix, classify its fields, and check the
 // classification on probes of both sides.
 int build_template(int op, const psvt_config *cfg, Template &T) {
-    int rc = batched_cfg(cfg, &T.side, &T.lp);
+    int rc = batched_cfg(cfg, &T.side, &T.lp, &T.persistent);
     if (rc) return rc;
     T.op = op;
     // template: a right-sided 333 x 201 matrix (unless the side is forced left)
@@ -381,7 +384,9 @@ int build_launches(const Template &T, std::vector<CountClass> &cls, std::vector<
             c.lit0 = g.g.M;
             c.lit1 = g.g.N;
             c.lit2 = g.g.K;
-            for (int tile = 1; tile <= kNumTiles; ++tile) {
+            // the persistent executor holds a smaller tile set (tilemodel.h)
+            const int hi = T.persistent ? kPersistMaxTile[g.dtype] : kNumTiles;
+            for (int tile = 1; tile <= hi; ++tile) {
                 c.tile = tile;
                 out.push_back(Launch{(int)k, tile, get(c), 0});
             }
@@ -404,21 +409,44 @@ int build_launches(const Template &T, std::vector<CountClass> &cls, std::vector<
     return PSVT_OK;
 }
 
+std::vector<PLaunch> plaunches(const std::vector<Launch> &launches) {
+    std::vector<PLaunch> pl(launches.size());
+    for (size_t j = 0; j < launches.size(); ++j)
+        pl[j] = PLaunch{launches[j].stage, (int16_t)launches[j].cls, (int8_t)launches[j].tile,
+                        (int8_t)launches[j].final_pass};
+    return pl;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Workspace: [records | prefix sums | sizes] then the matrices' workspaces.
+// Workspace: [persistent control | records | prefix sums | sizes | stage
+// templates | launches | first tickets | dependency counts | done counts]
+// then the matrices' workspaces.  The persistent areas are empty (nl = 0)
+// for the per-stage form.
 struct Areas {
-    size_t mats, prefix, need, area, total;
+    size_t ctl, mats, prefix, need, stages, launches, lbase, deps, done, area, total;
 };
-Areas areas(int32_t count, int ncls, size_t per_matrix) {
+Areas areas(int32_t count, int ncls, size_t per_matrix, int nstages = 0, int nl = 0) {
     Areas a;
     size_t off = 0;
+    a.ctl = off;
+    off = align256(off + (nl ? sizeof(PersistCtl) : 0));
     a.mats = off;
     off = align256(off + sizeof(MatInfo) * (size_t)count);
     a.prefix = off;
     off = align256(off + sizeof(int) * (size_t)ncls * ((size_t)count + 1));
     a.need = off;
     off = align256(off + sizeof(unsigned long long) * (size_t)count);
+    a.stages = off;
+    off = align256(off + (nl ? sizeof(StageT) * (size_t)nstages : 0));
+    a.launches = off;
+    off = align256(off + sizeof(PLaunch) * (size_t)nl);
+    a.lbase = off;
+    off = align256(off + (nl ? sizeof(int) * ((size_t)nl + 1) : 0));
+    a.deps = off;
+    off = align256(off + sizeof(int) * (size_t)count * (size_t)nl);
+    a.done = off;
+    off = align256(off + (nl ? sizeof(int) * (size_t)count : 0));
     a.area = off;
     a.total = off + per_matrix * (size_t)count;
     return a;
@@ -441,12 +469,34 @@ size_t per_matrix_bytes(int op, int64_t max_m, int64_t max_n, int lp) {
     return layout_for(op, std::max(max_m, max_n), std::min(max_m, max_n), true, lp != 0, false).total;
 }
 
+// The persistent executor numbers every item of the batch with an int.
+int check_persistent_size(int32_t count, int64_t max_m, int64_t max_n, int nl) {
+    const int64_t big = std::max(max_m, max_n);
+    const double per = (double)((big + 63) / 64) * (double)((big + 63) / 64) + NORM_PARTIALS;
+    if ((double)count * nl * per >= 2147483647.0) return set_error(PSVT_EINVAL, "batch too large for the persistent executor");
+    return PSVT_OK;
+}
+
 int batched_workspace(int op, int32_t count, int64_t max_m, int64_t max_n, const psvt_config *cfg, size_t *bytes) {
     int rc = check_shape_args(count, max_m, max_n);
     if (rc) return rc;
-    int side, lp;
-    if ((rc = batched_cfg(cfg, &side, &lp))) return rc;
-    *bytes = count ? areas(count, kMaxClasses, per_matrix_bytes(op, max_m, max_n, lp)).total : 0;
+    int side, lp, persistent;
+    if ((rc = batched_cfg(cfg, &side, &lp, &persistent))) return rc;
+    if (!count) {
+        *bytes = 0;
+        return PSVT_OK;
+    }
+    int nstages = 0, nl = 0;
+    if (persistent) {  // the tables' sizes come from the plan
+        Template T;
+        std::vector<CountClass> cls;
+        std::vector<Launch> launches;
+        if ((rc = build_template(op, cfg, T)) || (rc = build_launches(T, cls, launches))) return rc;
+        nstages = (int)T.kind.size();
+        nl = (int)launches.size();
+        if ((rc = check_persistent_size(count, max_m, max_n, nl))) return rc;
+    }
+    *bytes = areas(count, kMaxClasses, per_matrix_bytes(op, max_m, max_n, lp), nstages, nl).total;
     return PSVT_OK;
 }
 
@@ -461,7 +511,9 @@ int batched_run(int op, const psvt_desc *d_descs, int32_t count, int64_t max_m, 
     std::vector<CountClass> cls;
     std::vector<Launch> launches;
     if ((rc = build_launches(T, cls, launches))) return rc;
-    const Areas A = areas(count, kMaxClasses, per_matrix_bytes(op, max_m, max_n, T.lp));
+    const int nstages = T.persistent ? (int)T.kind.size() : 0, nl = T.persistent ? (int)launches.size() : 0;
+    if (T.persistent && (rc = check_persistent_size(count, max_m, max_n, nl))) return rc;
+    const Areas A = areas(count, kMaxClasses, per_matrix_bytes(op, max_m, max_n, T.lp), nstages, nl);
     if (!ws || ws_bytes < A.total)
         return set_error(PSVT_EWORKSPACE, "batched workspace missing or smaller than psvt_batched_workspace_bytes()");
     if (((uintptr_t)ws & 255) != 0) return set_error(PSVT_EINVAL, "workspace is not 256-byte aligned");
@@ -489,10 +541,47 @@ int batched_run(int op, const psvt_desc *d_descs, int32_t count, int64_t max_m, 
     sa.need = (unsigned long long *)(base + A.need);
     sa.ncls = (int)cls.size();
     for (size_t c = 0; c < cls.size(); ++c) sa.cls[c] = cls[c];
-    sa.model = tile_model();
+    sa.model = T.persistent ? tile_model_persistent() : tile_model();
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(batched_setup, dim3(1), dim3(1024), 0, st, sa);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(PSVT_EHIP, hipGetErrorString(e));
+    if (T.persistent) {
+        std::vector<StageT> stages(T.kind.size());
+        for (size_t k = 0; k < T.kind.size(); ++k) {
+            StageT &x = stages[k];
+            memset(&x, 0, sizeof x);
+            x.kind = T.kind[k];
+            x.dtype = T.dtype[k];
+            if (x.kind == ST_GEMM)
+                x.g = T.g[k];
+            else if (x.kind == ST_NORM)
+                x.n = T.n[k];
+            else
+                x.t = T.t[k];
+        }
+        const std::vector<PLaunch> pl = plaunches(launches);
+        if ((e = launch_upload(base + A.stages, stages.data(), sizeof(StageT) * stages.size(), st)) != hipSuccess ||
+            (e = launch_upload(base + A.launches, pl.data(), sizeof(PLaunch) * pl.size(), st)) != hipSuccess)
+            return set_error(PSVT_EHIP, hipGetErrorString(e));
+        PersistArgs pa;
+        memset(&pa, 0, sizeof pa);
+        pa.mats = sa.mats;
+        pa.count = count;
+        pa.op = op;
+        pa.lp = T.lp;
+        pa.status_on = sa.status_on;
+        pa.prefix = sa.prefix;
+        pa.launches = (const PLaunch *)(base + A.launches);
+        pa.nl = nl;
+        pa.stages = (const StageT *)(base + A.stages);
+        pa.lbase = (int *)(base + A.lbase);
+        pa.deps = (int *)(base + A.deps);
+        pa.done = (int *)(base + A.done);
+        pa.ctl = (PersistCtl *)(base + A.ctl);
+        pa.spin_limit = g_spin_limit;
+        if ((e = launch_persistent(pa, st)) != hipSuccess) return set_error(PSVT_EHIP, hipGetErrorString(e));
+        return PSVT_OK;
+    }
     BatchView v;
     v.mats = sa.mats;
     v.count = count;
@@ -512,9 +601,156 @@ int batched_run(int op, const psvt_desc *d_descs, int32_t count, int64_t max_m, 
     return PSVT_OK;
 }
 
+// Host replay of the persistent executor's schedule for the given shapes:
+// the records, count classes and tables the setup kernels would build (the
+// same functions), then checks that tickets map one to one onto items in
+// (launch, matrix, item) order, that an item's dependency count is the
+// matrix's items of earlier launches, and that `blocks` simulated blocks
+// taking tickets in order, with random item durations, drain every ticket,
+// each item starting only after its matrix's earlier launches completed.
+int check_schedule(int op, const int64_t *ms, const int64_t *ns, int32_t count, int64_t max_m, int64_t max_n,
+                   const psvt_config *cfg, int32_t blocks, uint64_t seed, int64_t *tickets) {
+    int rc = check_shape_args(count, max_m, max_n);
+    if (rc) return rc;
+    if (!ms || !ns || !tickets || blocks < 1) return set_error(PSVT_EINVAL, "bad arguments");
+    Template T;
+    if ((rc = build_template(op, cfg, T))) return rc;
+    T.persistent = 1;
+    std::vector<CountClass> cls;
+    std::vector<Launch> launches;
+    if ((rc = build_launches(T, cls, launches))) return rc;
+    const std::vector<PLaunch> pl = plaunches(launches);
+    const int nl = (int)pl.size();
+    const TileModelTable model = tile_model_persistent();
+    std::vector<MatInfo> mats(count);
+    for (int i = 0; i < count; ++i) {
+        MatInfo &mi = mats[i];
+        memset(&mi, 0, sizeof mi);
+        mi.m = ms[i];
+        mi.n = ns[i];
+        mi.valid = ms[i] >= 1 && ns[i] >= 1 && ms[i] <= max_m && ns[i] <= max_n;
+        mi.right = T.side == PSVT_SIDE_RIGHT ? 1 : T.side == PSVT_SIDE_LEFT ? 0 : (ns[i] < ms[i] ? 1 : 0);
+        mi.l = mi.right ? mi.m : mi.n;
+        mi.s = mi.right ? mi.n : mi.m;
+    }
+    const size_t cs = (size_t)count + 1;
+    std::vector<int> prefix(cls.size() * cs);
+    for (size_t c = 0; c < cls.size(); ++c) {
+        int run = 0;
+        for (int i = 0; i < count; ++i) {
+            prefix[c * cs + i] = run;
+            run += class_count(cls[c], mats[i], model);
+        }
+        prefix[c * cs + count] = run;
+    }
+    for (int j = 0; j < nl; ++j)
+        if (!pl[j].final_pass && prefix[(size_t)pl[j].cls * cs + count] > 0 && pl[j].tile > 0 &&
+            pl[j].tile > kPersistMaxTile[T.dtype[pl[j].stage]])
+            return set_error(PSVT_EINVAL, "schedule: a launch outside the executor's tile set has items");
+    std::vector<int> lbase(nl + 1), deps((size_t)count * nl);
+    {
+        int run = 0;
+        for (int j = 0; j < nl; ++j) {
+            lbase[j] = run;
+            run += persist_launch_items(pl[j], prefix.data(), count);
+        }
+        lbase[nl] = run;
+        for (int i = 0; i < count; ++i) {
+            int r = 0;
+            for (int j = 0; j < nl; ++j) {
+                deps[(size_t)i * nl + j] = r;
+                r += persist_items(pl[j], prefix.data(), count, i);
+            }
+        }
+    }
+    const int total = lbase[nl];
+    // tickets in (launch, matrix, item) order
+    {
+        int t = 0;
+        for (int j = 0; j < nl; ++j)
+            for (int i = 0; i < count; ++i)
+                for (int k = 0, n = persist_items(pl[j], prefix.data(), count, i); k < n; ++k, ++t) {
+                    int dj, di, dk;
+                    persist_decode(lbase.data(), nl, pl.data(), prefix.data(), count, t, dj, di, dk);
+                    if (dj != j || di != i || dk != k) {
+                        char msg[160];
+                        snprintf(msg, sizeof msg, "schedule: ticket %d decodes to (%d, %d, %d), not (%d, %d, %d)", t,
+                                 dj, di, dk, j, i, k);
+                        return set_error(PSVT_EINVAL, msg);
+                    }
+                }
+        if (t != total) return set_error(PSVT_EINVAL, "schedule: ticket count differs from the items");
+    }
+    // simulated blocks: take the next ticket when idle, wait for the
+    // matrix's dependency count, run for a random time
+    uint64_t x = seed * 2654435761ull + 0x9e3779b97f4a7c15ull;
+    auto rnd = [&]() {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        return x;
+    };
+    struct Blk {
+        int T, j, i;
+        int state;  // 0 idle, 1 waiting, 2 running
+        uint64_t end;
+    };
+    std::vector<Blk> b(blocks, Blk{-1, 0, 0, 0, 0});
+    std::vector<int> done(count, 0);
+    int next = 0, finished = 0;
+    uint64_t now = 0;
+    while (finished < total) {
+        bool progress = false;
+        for (Blk &k : b) {
+            if (k.state == 0 && next < total) {
+                k.T = next++;
+                int item;
+                persist_decode(lbase.data(), nl, pl.data(), prefix.data(), count, k.T, k.j, k.i, item);
+                k.state = 1;
+                progress = true;
+            }
+            if (k.state == 1) {
+                const int want = deps[(size_t)k.i * nl + k.j];
+                if (done[k.i] >= want) {
+                    // nothing of a later launch of this matrix may have completed
+                    if (done[k.i] >= want + persist_items(pl[k.j], prefix.data(), count, k.i))
+                        return set_error(PSVT_EINVAL, "schedule: an item ran after a later one of its matrix");
+                    k.state = 2;
+                    k.end = now + 1 + rnd() % 1000;
+                    progress = true;
+                }
+            }
+        }
+        int first = -1;
+        for (int q = 0; q < blocks; ++q)
+            if (b[q].state == 2 && (first < 0 || b[q].end < b[first].end)) first = q;
+        if (first < 0) {
+            if (!progress) return set_error(PSVT_EINVAL, "schedule: simulated blocks deadlock");
+            continue;
+        }
+        now = b[first].end;
+        ++done[b[first].i];
+        ++finished;
+        b[first].state = 0;
+    }
+    for (int i = 0; i < count; ++i)
+        if (done[i] != (nl ? deps[(size_t)i * nl + nl - 1] + persist_items(pl[nl - 1], prefix.data(), count, i) : 0))
+            return set_error(PSVT_EINVAL, "schedule: a matrix did not complete all its items");
+    *tickets = total;
+    return PSVT_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int psvt_batched_check_schedule(int op, const int64_t *ms, const int64_t *ns, int32_t count, int64_t max_m,
+                                int64_t max_n, const psvt_config *cfg, int32_t blocks, uint64_t seed,
+                                int64_t *tickets) {
+    if (op != PSVT_OP_SVT && op != PSVT_OP_RANK_R) return set_error(PSVT_EINVAL, "op must be svt or rank_r");
+    return check_schedule(op, ms, ns, count, max_m, max_n, cfg, blocks, seed, tickets);
+}
+
 
 int psvt_batched_workspace_bytes(int op, int32_t count, int64_t max_m, int64_t max_n, const psvt_config *cfg,
                                  size_t *bytes) {

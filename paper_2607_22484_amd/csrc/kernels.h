@@ -207,6 +207,9 @@ hipError_t gemm_launch_batched(const BatchView &v, const GemmStageT &s, int tile
 
 // The tile cost model as the calling thread sees it (tilemodel.h).
 TileModelTable tile_model();
+TileModelTable tile_model_persistent();
+void tune_persistent_tiles(int on);
+void set_persist_spin_limit(long long polls);  // the calling thread's bound on one persistent wait
 
 // Tile-configuration control (autotuner and tests).
 void tune_force_tile(int c);

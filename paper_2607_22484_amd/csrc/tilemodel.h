@@ -13,13 +13,20 @@ constexpr int kNumTiles = 4;
 
 __host__ __device__ inline int tile_bm(int c) { return c == 1 ? 64 : c == 2 ? 128 : c == 3 ? 192 : 256; }
 
+// Largest configuration per operand type (f32, bf16, fp8, split bf16) in
+// the persistent batched executor: one kernel holds every tile body it may
+// run, and these keep its LDS at two blocks per CU.
+constexpr int kPersistMaxTile[4] = {2, 2, 1, 1};
+
 // (efficiency, per-tile overhead in microseconds) per operand type, kind
 // (sym = lower-triangle product) and configuration 1..4; force: a forced
-// configuration (0 = none).
+// configuration (0 = none); max_tile: the largest configuration considered
+// per operand type.
 struct TileModelTable {
     float eff[4][2][kNumTiles + 1];
     float overhead_us[4][2][kNumTiles + 1];
     int force;
+    int max_tile[4];
 };
 
 __host__ __device__ inline int tile_count(int M, int N, int sym, int bm) {
@@ -44,10 +51,11 @@ __host__ __device__ inline double model_time_us(const TileModelTable &t, int typ
 }
 
 __host__ __device__ inline int pick_tile(const TileModelTable &t, int type, int M, int N, int K, int sym) {
-    if (t.force >= 1 && t.force <= kNumTiles) return t.force;
+    const int hi = t.max_tile[type] < kNumTiles ? t.max_tile[type] : kNumTiles;
+    if (t.force >= 1 && t.force <= hi) return t.force;
     double best = 1e300;
-    int arg = 2;
-    for (int c = 1; c <= kNumTiles; ++c) {
+    int arg = hi < 2 ? hi : 2;
+    for (int c = 1; c <= hi; ++c) {
         const double v = model_time_us(t, type, M, N, K, sym, c);
         if (v < best * 0.999) {
             best = v;
