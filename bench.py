@@ -225,31 +225,80 @@ def precision_leg(psvt, torch, dev, checks, problems=None):
     return out
 
 
+def desc_graph(psvt, torch, As, taus, Ys, flags=0, **kw):
+    """The device-described batched call (psvt_svt_batched) captured into a
+    HIP graph after one eager run; returns (graph, workspace, keep-alive)."""
+    cfg, keep = psvt.make_config(iters=20, flags=flags, **kw)
+    max_m = max(A.shape[0] for A in As)
+    max_n = max(A.shape[1] for A in As)
+    dev = As[0].device
+    ws = torch.empty(psvt.batched_workspace_bytes(len(As), max_m, max_n, cfg), dtype=torch.uint8, device=dev)
+    desc = psvt.device_descriptors(As, taus, Ys, None, dev)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        psvt.svt_batched_raw(desc.data_ptr(), len(As), max_m, max_n, ws, cfg)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        psvt.svt_batched_raw(desc.data_ptr(), len(As), max_m, max_n, ws, cfg)
+    return g, ws, (cfg, keep, desc)
+
+
 def batched_leg(psvt, torch, dev, checks, count=512):
-    """Batched form: 512 matrices, m, n log-uniform in [128, 2048], one graph
-    launch per batch."""
+    """Batched form: 512 matrices, m, n log-uniform in [128, 2048].  Rows:
+    the host-planned batch (psvt_batch_*: one graph of grouped launches),
+    the device-described batch (psvt_svt_batched) as one graph of per-stage
+    launches, and the persistent executor (PSVT_FLAG_PERSISTENT: one
+    persistent launch after the setup kernels, graph-captured), per
+    precision schedule."""
     from paper_2607_22484_amd import inputs
     pbs = inputs.batch_cases(count=count)
     As = [torch.from_numpy(p.A).to(dev) for p in pbs]
     taus = [p.tau for p in pbs]
     out = {"matrices": count}
+
+    def add_check(row, Ys):
+        if checks is None:
+            return
+        Yh = [Y.cpu().numpy() for Y in Ys]
+
+        def check(oracle, Yh=Yh, dst=row):
+            dst["worst_rel_err"] = max(
+                oracle.rel_fro_err(Y.astype(np.float64), oracle.svt_from_svd(p.U, p.sigma, p.V, p.tau))
+                for p, Y in zip(pbs, Yh))
+        checks.append(check)
+
+    useful = None
     for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)),
-                     ("bf16_plainP", dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P))]:
+                     ("bf16_plainP", dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P)), ("split_bf16_all", dict(n_bf16=20))]:
         b = psvt.Batch(As, taus, iters=20, **kw)
         nl, fl = b.stats()
+        useful = useful or fl
         ms = time_calls(torch, b.run_graph, 3)
         row = {"ms_per_batch": ms, "matrices_per_s": count / (ms * 1e-3), "useful_tflops": fl / (ms * 1e-3) / 1e12,
                "launches_in_graph": nl}
-        if checks is not None:
-            Yh = [Y.cpu().numpy() for Y in b.Ys]
-
-            def check(oracle, Yh=Yh, dst=row):
-                dst["worst_rel_err"] = max(
-                    oracle.rel_fro_err(Y.astype(np.float64), oracle.svt_from_svd(p.U, p.sigma, p.V, p.tau))
-                    for p, Y in zip(pbs, Yh))
-            checks.append(check)
+        add_check(row, b.Ys)
         out[name] = row
         b.close()
+        print("[bench] batched %s: %.0f matrices/s" % (name, row["matrices_per_s"]), file=sys.stderr, flush=True)
+    # device-described: per-stage launches and the persistent executor
+    for name, kw in [("fp32", dict()), ("bf16", dict(n_bf16=18)), ("split_bf16_all", dict(n_bf16=20))]:
+        for form, flags in (("desc_staged", 0), ("persistent", psvt.FLAG_PERSISTENT)):
+            Ys = [torch.empty_like(A) for A in As]
+            g, ws, keep = desc_graph(psvt, torch, As, taus, Ys, flags=flags, **kw)
+            ms = time_calls(torch, g.replay, 3)
+            row = {"ms_per_batch": ms, "matrices_per_s": count / (ms * 1e-3),
+                   "useful_tflops": useful / (ms * 1e-3) / 1e12}
+            if flags:
+                row["aborted"] = psvt.persistent_aborted(ws)
+            add_check(row, Ys)
+            out["%s_%s" % (form, name)] = row
+            print("[bench] batched %s_%s: %.0f matrices/s" % (form, name, row["matrices_per_s"]), file=sys.stderr,
+                  flush=True)
+            del g, ws, keep, Ys
+            torch.cuda.empty_cache()
     # the plain FP32 form on the same matrices: one matrix per launch sequence
     cfg, _ = psvt.make_config(iters=20)
     ws = torch.empty(max(psvt.workspace_bytes(psvt.OP_SVT, p.shape[0], p.shape[1], cfg) for p in pbs),
@@ -278,7 +327,12 @@ def small_leg(psvt, torch, dev, checks, reps=50):
     b = psvt.Batch([A], [pb.tau], iters=20)
     graph_ms = time_calls(torch, b.run_graph, reps)
     nl, _ = b.stats()
-    out = {"shape": list(pb.A.shape), "eager_us": 1e3 * eager_ms, "graph_us": 1e3 * graph_ms, "launches": nl}
+    Yp = torch.empty_like(A)
+    g, pws, keep = desc_graph(psvt, torch, [A], [pb.tau], [Yp], flags=psvt.FLAG_PERSISTENT)
+    persist_ms = time_calls(torch, g.replay, reps)
+    out = {"shape": list(pb.A.shape), "eager_us": 1e3 * eager_ms, "graph_us": 1e3 * graph_ms, "launches": nl,
+           "persistent_graph_us": 1e3 * persist_ms, "persistent_aborted": psvt.persistent_aborted(pws)}
+    del g, pws, keep
     if checks is not None:
         Yh = b.Ys[0].cpu().numpy().astype(np.float64)
 

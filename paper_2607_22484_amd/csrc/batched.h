@@ -156,10 +156,6 @@ __host__ __device__ inline void relocate_gemm(const GemmStageT &st, const MatInf
     gemm_prepare(g, st.dtype);
 }
 
-__host__ __device__ inline int norm_parts(int64_t rows) {
-    return (int)(rows < NORM_PARTIALS ? (rows < 1 ? 1 : rows) : NORM_PARTIALS);
-}
-
 __host__ __device__ inline void relocate_norm(const NormStageT &st, const MatInfo &mi, int op, int lp, NormOp &n) {
     const Layout L = mat_layout(mi, op, lp);
     const NormReloc &r = st.r;
@@ -172,7 +168,7 @@ __host__ __device__ inline void relocate_norm(const NormStageT &st, const MatInf
     if (r.sc) n.sc = (Scalars *)(mi.base + L.scal);
     if (r.status) n.status = mi.status;
     if (r.tau) n.tau = mi.tau;
-    n.nparts = norm_parts(n.rows);
+    n.nparts = norm_parts(n.rows, n.cols);
 }
 
 __host__ __device__ inline void relocate_tile(const TileStageT &st, const MatInfo &mi, int op, int lp, TileOp &t) {
@@ -220,8 +216,9 @@ enum CountKind { CK_GEMM = 0, CK_NORM = 1, CK_TILE = 2 };
 struct CountClass {
     int kind;
     int dtype, sym, tile;     // CK_GEMM: tiles of configuration `tile` when the model picks it
-    uint8_t c0, c1, c2;       // dim codes: M, N, K (gemm); rows (norm); rows, cols (tile)
+    uint8_t c0, c1, c2;       // dim codes: M, N, K (gemm); rows, cols (norm, tile)
     int lit0, lit1, lit2;     // their literal values when coded DC_LIT
+    int group;                // CK_TILE: 64 x 64 tiles per item (>= 1)
 };
 
 __host__ __device__ inline int class_count(const CountClass &c, const MatInfo &mi, const TileModelTable &model) {
@@ -232,8 +229,9 @@ __host__ __device__ inline int class_count(const CountClass &c, const MatInfo &m
         if (pick_tile(model, c.dtype, (int)d0, (int)d1, (int)d2, c.sym) != c.tile) return 0;
         return tile_count((int)d0, (int)d1, c.sym, tile_bm(c.tile));
     }
-    if (c.kind == CK_NORM) return norm_parts(d0);
-    return (int)(((d0 + 63) / 64) * ((d1 + 63) / 64));
+    if (c.kind == CK_NORM) return norm_parts(d0, d1);
+    const int64_t tiles = ((d0 + 63) / 64) * ((d1 + 63) / 64);
+    return (int)((tiles + c.group - 1) / c.group);
 }
 
 // ----------------------------------------------- persistent executor
@@ -246,6 +244,9 @@ __host__ __device__ inline int class_count(const CountClass &c, const MatInfo &m
 // unfinished ticket can always run and the launch drains.  Waits are
 // bounded: past the bound a block raises the abort flag, every later item
 // is skipped, and the kernel still ends.
+
+// 64 x 64 elementwise tiles per item of the persistent executor.
+constexpr int kPersistTileGroup = 8;
 
 // A template stage as the persistent kernel reads it.
 struct StageT {
@@ -262,7 +263,7 @@ struct StageT {
 struct PLaunch {
     int32_t stage;
     int16_t cls;
-    int8_t tile, final_pass;
+    int8_t tile, final_pass;  // tile: gemm configuration, or tile-op tiles per item
 };
 
 // At byte 0 of the workspace of a persistent call: the ticket counter and the

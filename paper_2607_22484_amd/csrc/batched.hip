@@ -361,10 +361,10 @@ struct Launch {
     int stage, tile, cls, final_pass;
 };
 int build_launches(const Template &T, std::vector<CountClass> &cls, std::vector<Launch> &out) {
-    std::map<std::tuple<int, int, int, int, int, int, int, int, int, int>, int> index;
+    std::map<std::tuple<int, int, int, int, int, int, int, int, int, int, int>, int> index;
     auto get = [&](const CountClass &c) {
         auto key = std::make_tuple(c.kind, c.dtype, c.sym, c.tile, (int)c.c0, (int)c.c1, (int)c.c2, c.lit0, c.lit1,
-                                   c.lit2);
+                                   c.lit2, c.group);
         auto it = index.find(key);
         if (it != index.end()) return it->second;
         cls.push_back(c);
@@ -373,6 +373,7 @@ int build_launches(const Template &T, std::vector<CountClass> &cls, std::vector<
     for (size_t k = 0; k < T.kind.size(); ++k) {
         CountClass c;
         memset(&c, 0, sizeof c);
+        c.group = 1;
         if (T.kind[k] == ST_GEMM) {
             const GemmStageT &g = T.g[k];
             c.kind = CK_GEMM;
@@ -394,6 +395,8 @@ int build_launches(const Template &T, std::vector<CountClass> &cls, std::vector<
             c.kind = CK_NORM;
             c.c0 = T.n[k].r.rows;
             c.lit0 = (int)T.n[k].n.rows;
+            c.c1 = T.n[k].r.cols;
+            c.lit1 = (int)T.n[k].n.cols;
             out.push_back(Launch{(int)k, 0, get(c), 0});
             out.push_back(Launch{(int)k, 0, -1, 1});
         } else {
@@ -402,7 +405,10 @@ int build_launches(const Template &T, std::vector<CountClass> &cls, std::vector<
             c.c1 = T.t[k].r.cols;
             c.lit0 = (int)T.t[k].t.rows;
             c.lit1 = (int)T.t[k].t.cols;
-            out.push_back(Launch{(int)k, 0, get(c), 0});
+            // the persistent executor takes several elementwise tiles per
+            // item (one ticket and one pair of fences each)
+            c.group = T.persistent ? kPersistTileGroup : 1;
+            out.push_back(Launch{(int)k, c.group, get(c), 0});
         }
     }
     if ((int)cls.size() > kMaxClasses) return set_error(PSVT_EINVAL, "internal: too many count classes");
@@ -644,7 +650,7 @@ int check_schedule(int op, const int64_t *ms, const int64_t *ns, int32_t count, 
         prefix[c * cs + count] = run;
     }
     for (int j = 0; j < nl; ++j)
-        if (!pl[j].final_pass && prefix[(size_t)pl[j].cls * cs + count] > 0 && pl[j].tile > 0 &&
+        if (T.kind[pl[j].stage] == ST_GEMM && prefix[(size_t)pl[j].cls * cs + count] > 0 &&
             pl[j].tile > kPersistMaxTile[T.dtype[pl[j].stage]])
             return set_error(PSVT_EINVAL, "schedule: a launch outside the executor's tile set has items");
     std::vector<int> lbase(nl + 1), deps((size_t)count * nl);

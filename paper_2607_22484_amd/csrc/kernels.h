@@ -192,6 +192,20 @@ enum NormMode {
 enum StatusBits { ST_NONFINITE_INPUT = 1, ST_NONFINITE_OUTPUT = 2, ST_NOT_CONVERGED = 4 };
 
 constexpr int NORM_PARTIALS = 1024;
+constexpr int64_t NORM_PART_ELEMS = 65536;
+
+// Partial sums of one norm: at most four rows or 64K elements per part
+// (whichever gives more parts: short chains of dependent loads per block),
+// at most one part per row and NORM_PARTIALS parts.  Every path uses this
+// count, so every path sums in the same order.
+__host__ __device__ inline int norm_parts(int64_t rows, int64_t cols) {
+    int64_t p = (rows * cols + NORM_PART_ELEMS - 1) / NORM_PART_ELEMS;
+    const int64_t by_rows = (rows + 3) / 4;
+    if (p < by_rows) p = by_rows;
+    if (p > rows) p = rows;
+    if (p > NORM_PARTIALS) p = NORM_PARTIALS;
+    return (int)(p < 1 ? 1 : p);
+}
 
 // Device-described batches (batched.h): one launch per stage (products: per
 // tile configuration), enqueue only.

@@ -187,7 +187,7 @@ NormOp make_norm_op(const float *X, int64_t rows, int64_t cols, int64_t ld, doub
     op.cols = cols;
     op.ld = ld;
     op.part = partials;
-    op.nparts = (int)(rows < NORM_PARTIALS ? (rows < 1 ? 1 : rows) : NORM_PARTIALS);
+    op.nparts = norm_parts(rows, cols);
     op.sc = sc;
     op.mode = mode;
     op.tau = tau;

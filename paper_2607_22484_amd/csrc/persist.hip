@@ -5,9 +5,10 @@
 // bitwise those of single calls that use the same tile configurations.
 //
 // Memory ordering between blocks: a block that completes an item makes its
-// stores visible at agent scope (a release fence in every wave, then the
-// counter increment); a block that has waited for a counter takes an
-// acquire fence in every wave before it reads what the item depends on.
+// stores visible at agent scope (each wave waits for its stores, then one
+// release fence, then the counter increment); a block that has waited for a
+// counter takes an acquire fence before the barrier after which its waves
+// read what the item depends on.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -99,8 +100,11 @@ __device__ int wait_ready(const PersistArgs &a, int i, int want) {
             return 0;
         }
         if (__builtin_amdgcn_readfirstlane(load_agent(&a.ctl->abort))) return 0;
-        __builtin_amdgcn_s_sleep(4);
+        __builtin_amdgcn_s_sleep(16);
     }
+    // acquire at agent scope: this CU's L1 and the L2 drop stale lines, for
+    // every wave of the block (they read only after the barrier that follows)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return 2;
 }
 
@@ -162,11 +166,18 @@ __device__ __attribute__((noinline)) void norm_call(const StageT *S, const MatIn
     }
 }
 
-__device__ __attribute__((noinline)) void tile_call(const StageT *S, const MatInfo *mip, int op, int lp, int item) {
+// Tiles [item * group, (item + 1) * group) of an elementwise stage.
+__device__ __attribute__((noinline)) void tile_call(const StageT *S, const MatInfo *mip, int op, int lp, int item,
+                                                    int group) {
     const MatInfo mi = *mip;
     TileOp t;
     relocate_tile(S->t, mi, op, lp, t);
-    tile_op_body(t, item, (float(*)[65])persist_lds);
+    const int tiles = __builtin_amdgcn_readfirstlane((int)(((t.rows + 63) / 64) * ((t.cols + 63) / 64)));
+    const int t0 = item * group, t1 = t0 + group < tiles ? t0 + group : tiles;
+    for (int k = t0; k < t1; ++k) {
+        tile_op_body(t, k, (float(*)[65])persist_lds);
+        __syncthreads();  // the next tile refills LDS
+    }
 }
 
 // Returns false for a configuration outside the executor's tile set.
@@ -188,7 +199,7 @@ __device__ __forceinline__ bool run_item(const PersistArgs &a, const PLaunch &L,
     if (kind == ST_NORM)
         norm_call(S, mi, a.op, a.lp, item, L.final_pass);
     else
-        tile_call(S, mi, a.op, a.lp, item);
+        tile_call(S, mi, a.op, a.lp, item, L.tile);
     return true;
 }
 
@@ -225,12 +236,16 @@ __global__ __launch_bounds__(256, kPersistBlocksPerCU) void batched_persistent(P
         __syncthreads();
         const int go = __builtin_amdgcn_readfirstlane(s_go);
         if (go) {
-            if (go == 2) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const bool ok = run_item(a, L, i, item);
             if (!ok && wave0) abort_batch(a);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();  // every wave's stores are released; LDS is free for the next item
+        // release: every wave waits until its own stores have reached the
+        // L2 (vmcnt 0), then, after the barrier, wave 0 alone writes the L2
+        // back at agent scope (one write-back per item instead of one per
+        // wave) before it counts the item done
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt unconstrained
+        __syncthreads();                     // LDS is free for the next item, too
+        if (wave0) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         prev = i;
     }
 }
