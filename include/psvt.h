@@ -390,16 +390,33 @@ int psvt_batch_destroy(psvt_batch *batch);
  *            ready once poll / wait report state 2 (done).
  *            PSVT_EWORKSPACE if the request could never fit the budget.
  *   poll / wait:  state 0 queued, 1 running, 2 done, -1 failed.
- *   drain:   waits until nothing is queued or active.
- *   stats:   latency = completion observed by the worker - submit time. */
+ *   drain:   waits until nothing is queued or active; returns the first
+ *            launch error the server met, if any (requests of other ticks
+ *            and lanes are not affected by it).
+ *   stats:   latency = completion observed by the worker - submit time.
+ * Failures stay with their requests: a request whose plan fails, whose
+ * submitter event cannot be waited for, or that passes its deadline fails
+ * alone; a launch error fails the requests of that tick (they share its
+ * launches), and the lane goes on with its other requests.  The workspace
+ * of a request failed while its stages may be in flight returns to the pool
+ * once its lane's last tick has passed on the device.
+ *   set_timeout:  a request not done `seconds` after its submit fails
+ *            (state -1, counted in timed_out); 0 (the default) = none.
+ *   inject_fault: PSVT_SERVER_FAKE servers only (tests of the failure
+ *            paths): PSVT_FAULT_TICK fails the n-th tick (counted over all
+ *            lanes from 0) as a launch error would; PSVT_FAULT_PLAN fails
+ *            the n-th admission's plan; PSVT_FAULT_STALL with n != 0 stops
+ *            fake ticks from completing, n = 0 lets them complete again. */
 #define PSVT_SERVER_FAKE 0x1u
 #define PSVT_SERVER_COHORT 0x2u
 #define PSVT_SERVER_EAGER 0x4u
 typedef struct psvt_server psvt_server;
+enum { PSVT_FAULT_TICK = 1, PSVT_FAULT_PLAN = 2, PSVT_FAULT_STALL = 3 };
 typedef struct psvt_server_counters {
     int64_t submitted, completed, failed, queued, active, ticks, launches;
     double p50_ms, p99_ms, max_ms, queue_p99_ms, matrices_per_s;
     size_t budget_bytes, peak_bytes;
+    int64_t timed_out; /* failed requests that passed their deadline */
 } psvt_server_counters;
 int psvt_server_create(size_t budget_bytes, int32_t max_slots, const psvt_config *cfg, uint32_t flags,
                        psvt_server **out);
@@ -408,6 +425,8 @@ int psvt_server_poll(psvt_server *server, uint64_t ticket, int32_t *state);
 int psvt_server_wait(psvt_server *server, uint64_t ticket, double timeout_s, int32_t *state);
 int psvt_server_drain(psvt_server *server, double timeout_s);
 int psvt_server_stats(psvt_server *server, psvt_server_counters *stats);
+int psvt_server_set_timeout(psvt_server *server, double seconds);
+int psvt_server_inject_fault(psvt_server *server, int kind, int64_t n);
 int psvt_server_destroy(psvt_server *server);
 
 /* Building blocks exposed for kernel-level tests and tuning.

@@ -37,9 +37,11 @@ EXPORTED = [
     "psvt_tune_spin_limit", "psvt_batched_workspace_bytes", "psvt_batched_check_schedule", "psvt_svt_batched", "psvt_rank_r_batched",
     "psvt_batch_workspace_bytes", "psvt_batch_create", "psvt_batch_run", "psvt_batch_run_graph", "psvt_batch_stats",
     "psvt_batch_destroy", "psvt_server_create", "psvt_server_submit", "psvt_server_poll", "psvt_server_wait",
-    "psvt_server_drain", "psvt_server_stats", "psvt_server_destroy",
+    "psvt_server_drain", "psvt_server_stats", "psvt_server_set_timeout", "psvt_server_inject_fault",
+    "psvt_server_destroy",
 ]
 SERVER_FAKE, SERVER_COHORT, SERVER_EAGER = 0x1, 0x2, 0x4
+FAULT_TICK, FAULT_PLAN, FAULT_STALL = 1, 2, 3
 RQ_QUEUED, RQ_RUNNING, RQ_DONE, RQ_FAILED = 0, 1, 2, -1
 TILE_IDS = {64: 1, 128: 2, 192: 3, 256: 4}
 TUNE_TABLE = os.path.join(_HERE, "tune_table.txt")
@@ -91,7 +93,7 @@ class ServerCounters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "queued", "active", "ticks",
                                               "launches")] + \
                [(k, ctypes.c_double) for k in ("p50_ms", "p99_ms", "max_ms", "queue_p99_ms", "matrices_per_s")] + \
-               [("budget_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t)]
+               [("budget_bytes", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("timed_out", ctypes.c_int64)]
 
 
 class TraceStat(ctypes.Structure):
@@ -169,9 +171,12 @@ def load(path: Optional[str] = None):
     lib.psvt_server_wait.argtypes = [srv, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_int32)]
     lib.psvt_server_drain.argtypes = [srv, ctypes.c_double]
     lib.psvt_server_stats.argtypes = [srv, ctypes.POINTER(ServerCounters)]
+    lib.psvt_server_set_timeout.argtypes = [srv, ctypes.c_double]
+    lib.psvt_server_inject_fault.argtypes = [srv, ctypes.c_int, i64]
     lib.psvt_server_destroy.argtypes = [srv]
     for f in ("psvt_server_create", "psvt_server_submit", "psvt_server_poll", "psvt_server_wait",
-              "psvt_server_drain", "psvt_server_stats", "psvt_server_destroy"):
+              "psvt_server_drain", "psvt_server_stats", "psvt_server_set_timeout", "psvt_server_inject_fault",
+              "psvt_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     lib.psvt_trace_begin.restype = ctypes.c_int
     lib.psvt_trace_end.restype = ctypes.c_int
@@ -687,6 +692,15 @@ class Server:
     def drain(self, timeout: float = 600.0):
         _check(load().psvt_server_drain(self._h, float(timeout)), "psvt_server_drain")
         self._pinned.clear()
+
+    def set_timeout(self, seconds: float):
+        """Requests not done ``seconds`` after submit fail (0 = none)."""
+        _check(load().psvt_server_set_timeout(self._h, float(seconds)), "psvt_server_set_timeout")
+
+    def inject_fault(self, kind: int, n: int):
+        """Fake servers: FAULT_TICK fails tick n, FAULT_PLAN the n-th plan,
+        FAULT_STALL (n != 0) stops fake ticks from completing."""
+        _check(load().psvt_server_inject_fault(self._h, int(kind), int(n)), "psvt_server_inject_fault")
 
     def stats(self) -> dict:
         c = ServerCounters()

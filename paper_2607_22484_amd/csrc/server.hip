@@ -207,8 +207,21 @@ struct psvt_server {
     int error = PSVT_OK;
     std::vector<hipEvent_t> free_events;  // ready events of finished requests
 
+    // request deadline (seconds from submit; 0 = none) and the workspaces of
+    // failed requests that the lane's in-flight ticks may still use
+    double timeout_s = 0.0;
+    struct Pending {
+        int lane;
+        int64_t tick;
+        size_t off, bytes;
+    };
+    std::vector<Pending> pending;
+    // fault injection (fake servers: tests of the failure paths)
+    int64_t fault_tick = -1, fault_plan = -1, plans = 0;
+    bool stall = false;
+
     // statistics
-    int64_t submitted = 0, completed = 0, failed = 0, ticks = 0, launches = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, timed_out = 0, ticks = 0, launches = 0;
     std::vector<double> latency_ms, queue_ms;
     double first_submit = -1, last_done = -1;
 };
@@ -317,14 +330,27 @@ int launch_tick(psvt_server *s, psvt_server::Lane &lane, int seg, size_t seg_use
     return PSVT_OK;
 }
 
-void finish(psvt_server *s, Request *r, int state) {
+// Whether lane tick `tick` has finished on the device (fake: at once).
+bool tick_passed(psvt_server *s, int lane, int64_t tick) {
+    if (s->fake || tick < 0) return true;
+    const psvt_server::Lane &ln = s->lanes[lane];
+    const int seg = (int)(tick % s->nseg);
+    return ln.seg_tick[seg] != tick || hipEventQuery(ln.seg_event[seg]) == hipSuccess;
+}
+
+// keep_ws: the request's stages may still be in flight on its lane; its
+// workspace returns to the pool once the lane's latest tick has passed.
+void finish(psvt_server *s, Request *r, int state, bool keep_ws = false) {
     r->state = state;
     r->t_done = now_s();
-    if (r->ready) {  // complete: the lane waited for it before the request's first stage
-        s->free_events.push_back(r->ready);
+    if (r->ready) {  // the lane waited for it before the request's first stage (or never will)
+        if (!keep_ws) s->free_events.push_back(r->ready);  // else an in-flight wait may still name it
         r->ready = nullptr;
     }
-    if (s->pool) s->pool->release(r->ws_off, r->ws_bytes);
+    if (s->pool && r->ws_bytes && !keep_ws) s->pool->release(r->ws_off, r->ws_bytes);
+    if (s->pool && r->ws_bytes && keep_ws)
+        s->pending.push_back(psvt_server::Pending{r->lane, s->lanes[r->lane].tick - 1, r->ws_off, r->ws_bytes});
+    r->ws_bytes = 0;
     r->plan.clear();
     r->plan.shrink_to_fit();
     if (state == RQ_DONE) {
@@ -341,6 +367,35 @@ void worker_main(psvt_server *s) {
     if (!s->fake) (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
+        const double t_now = now_s();
+        // workspaces of failed requests whose lane has passed their stages
+        for (size_t i = 0; i < s->pending.size();) {
+            const psvt_server::Pending &p = s->pending[i];
+            if (tick_passed(s, p.lane, p.tick)) {
+                s->pool->release(p.off, p.bytes);
+                s->pending[i] = s->pending.back();
+                s->pending.pop_back();
+            } else {
+                ++i;
+            }
+        }
+        // queued requests past their deadline fail without running
+        if (s->timeout_s > 0.0) {
+            bool any = false;
+            for (auto it = s->queue.begin(); it != s->queue.end();) {
+                Request *r = *it;
+                if (t_now - r->t_submit > s->timeout_s) {
+                    r->ws_bytes = 0;  // never admitted: nothing in the pool
+                    finish(s, r, RQ_FAILED);
+                    s->timed_out++;
+                    it = s->queue.erase(it);
+                    any = true;
+                } else {
+                    ++it;
+                }
+            }
+            if (any) s->cv_done.notify_all();
+        }
         // admission: arrival order, one slot and pool room per request
         while (!s->queue.empty() && (int)s->active.size() < s->max_slots) {
             Request *r = s->queue.front();
@@ -348,8 +403,9 @@ void worker_main(psvt_server *s) {
             if (!s->pool->alloc(r->ws_bytes, &off)) break;  // wait for memory (no overtaking)
             r->ws_off = off;
             r->plan.clear();
-            const int rc = plan_request(r->op, r->item, s->fake ? (void *)(uintptr_t)(4096 + off) : s->pool_dev + off,
-                                        &s->cfg, r->plan, &r->ws_bytes, !s->fake, r->cut);
+            int rc = plan_request(r->op, r->item, s->fake ? (void *)(uintptr_t)(4096 + off) : s->pool_dev + off,
+                                  &s->cfg, r->plan, &r->ws_bytes, !s->fake, r->cut);
+            if (s->fake && s->plans++ == s->fault_plan) rc = set_error(PSVT_EINVAL, "injected planning failure");
             r->cursor = 0;
             r->curP = r->cut[0];
             r->curS = r->cut[1];
@@ -370,22 +426,21 @@ void worker_main(psvt_server *s) {
                     }
             s->active.push_back(r);
         }
-        // completions
+        // completions, and active requests past their deadline (only this
+        // request fails; its workspace waits for its lane's in-flight ticks)
         bool any_done = false;
         for (size_t i = 0; i < s->active.size();) {
             Request *r = s->active[i];
-            bool done = false;
-            if (r->finish_tick >= 0) {
-                if (s->fake) {
-                    done = true;
+            bool done = false, late = false;
+            if (r->finish_tick >= 0) done = s->fake ? !s->stall : tick_passed(s, r->lane, r->finish_tick);
+            if (!done && s->timeout_s > 0.0 && t_now - r->t_submit > s->timeout_s) late = true;
+            if (done || late) {
+                if (done) {
+                    finish(s, r, RQ_DONE);
                 } else {
-                    const psvt_server::Lane &ln = s->lanes[r->lane];
-                    const int seg = (int)(r->finish_tick % s->nseg);
-                    done = ln.seg_tick[seg] != r->finish_tick || hipEventQuery(ln.seg_event[seg]) == hipSuccess;
+                    finish(s, r, RQ_FAILED, r->cursor + r->curP + r->curS > 0);
+                    s->timed_out++;
                 }
-            }
-            if (done) {
-                finish(s, r, RQ_DONE);
                 s->active[i] = s->active.back();
                 s->active.pop_back();
                 any_done = true;
@@ -434,6 +489,26 @@ void worker_main(psvt_server *s) {
             // reuse the lane's oldest segment only once its tick has finished
             const int seg = (int)(ln.tick % s->nseg);
             if (!s->fake && ln.seg_tick[seg] >= 0 && hipEventQuery(ln.seg_event[seg]) != hipSuccess) continue;
+            // order each newcomer after its submitter's stream; a request
+            // whose wait cannot be enqueued fails alone (nothing of it ran)
+            if (!s->fake) {
+                std::vector<Request *> ok;
+                for (Request *r : runnable) {
+                    if (r->ready && !r->waited) {
+                        if (hipStreamWaitEvent(ln.stream, r->ready, 0) != hipSuccess) {
+                            (void)hipGetLastError();
+                            finish(s, r, RQ_FAILED);
+                            s->active.erase(std::find(s->active.begin(), s->active.end(), r));
+                            s->cv_done.notify_all();
+                            continue;
+                        }
+                        r->waited = true;
+                    }
+                    ok.push_back(r);
+                }
+                runnable.swap(ok);
+                if (runnable.empty()) continue;
+            }
             size_t seg_used = 0;
             int rc = PSVT_OK;
             std::vector<Group> gl;
@@ -444,13 +519,8 @@ void worker_main(psvt_server *s) {
                 if (rr.empty()) break;
                 rc = build_round(s, ln, rr, seg, seg_used, gl);
             }
-            if (rc == PSVT_OK && !s->fake)
-                for (Request *r : runnable)
-                    if (r->ready && !r->waited) {
-                        const hipError_t e = hipStreamWaitEvent(ln.stream, r->ready, 0);
-                        if (e != hipSuccess) rc = set_error(PSVT_EHIP, hipGetErrorString(e));
-                        r->waited = true;
-                    }
+            if (rc == PSVT_OK && s->fake && s->ticks == s->fault_tick)
+                rc = set_error(PSVT_EHIP, "injected launch failure");
             if (rc == PSVT_OK) rc = launch_tick(s, ln, seg, seg_used, gl);
             if (!s->fake) {
                 (void)hipEventRecord(ln.seg_event[seg], ln.stream);
@@ -462,19 +532,26 @@ void worker_main(psvt_server *s) {
             ++ln.tick;
             launched = true;
             if (rc != PSVT_OK) {
-                // the lane's earlier ticks may still use these workspaces:
-                // release them only once the lane's stream is idle
+                // this tick's launches are shared by its requests: they fail
+                // (other lanes, and this lane's later requests, go on); the
+                // lane's earlier ticks may still use their workspaces, which
+                // return to the pool once those ticks have passed
                 s->error = rc;
-                if (!s->fake) (void)hipStreamSynchronize(ln.stream);
                 for (Request *r : runnable) {
-                    finish(s, r, RQ_FAILED);
+                    finish(s, r, RQ_FAILED, true);
                     s->active.erase(std::find(s->active.begin(), s->active.end(), r));
                 }
                 s->cv_done.notify_all();
             }
         }
         if (!any_runnable) {
-            if (s->stop && s->queue.empty() && s->active.empty()) break;
+            if (s->stop && s->queue.empty() && s->active.empty()) {
+                if (!s->fake)
+                    for (auto &ln : s->lanes) (void)hipStreamSynchronize(ln.stream);
+                for (const psvt_server::Pending &p : s->pending) s->pool->release(p.off, p.bytes);
+                s->pending.clear();
+                break;
+            }
             // wait for arrivals or for in-flight ticks to finish
             s->cv_work.wait_for(lk, std::chrono::microseconds(s->active.empty() ? 2000 : 50));
         } else if (!launched) {
@@ -643,7 +720,9 @@ int psvt_server_drain(psvt_server *s, double timeout_s) {
     while (!s->queue.empty() || !s->active.empty())
         if (s->cv_done.wait_until(lk, until) == std::cv_status::timeout)
             return set_error(PSVT_EINVAL, "drain timed out");
-    return s->error;
+    if (s->error != PSVT_OK)  // the worker's message is on its own thread
+        return set_error(s->error, "a launch failed in the server: the requests of that tick failed");
+    return PSVT_OK;
 }
 
 int psvt_server_stats(psvt_server *s, psvt_server_counters *st) {
@@ -653,6 +732,7 @@ int psvt_server_stats(psvt_server *s, psvt_server_counters *st) {
     st->submitted = s->submitted;
     st->completed = s->completed;
     st->failed = s->failed;
+    st->timed_out = s->timed_out;
     st->queued = (int64_t)s->queue.size();
     st->active = (int64_t)s->active.size();
     st->ticks = s->ticks;
@@ -665,6 +745,33 @@ int psvt_server_stats(psvt_server *s, psvt_server_counters *st) {
     st->matrices_per_s = (s->completed > 0 && span > 0) ? s->completed / span : 0.0;
     st->budget_bytes = s->budget;
     st->peak_bytes = s->pool->peak();
+    return PSVT_OK;
+}
+
+int psvt_server_set_timeout(psvt_server *s, double seconds) {
+    if (!s) return set_error(PSVT_EINVAL, "NULL server");
+    if (!(seconds >= 0.0) || seconds > 1e9) return set_error(PSVT_EINVAL, "timeout outside [0, 1e9] seconds");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->timeout_s = seconds;
+    }
+    s->cv_work.notify_all();
+    return PSVT_OK;
+}
+
+int psvt_server_inject_fault(psvt_server *s, int kind, int64_t n) {
+    if (!s) return set_error(PSVT_EINVAL, "NULL server");
+    if (!s->fake) return set_error(PSVT_EINVAL, "fault injection is for PSVT_SERVER_FAKE servers");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        switch (kind) {
+            case PSVT_FAULT_TICK: s->fault_tick = n; break;
+            case PSVT_FAULT_PLAN: s->fault_plan = n; break;
+            case PSVT_FAULT_STALL: s->stall = n != 0; break;
+            default: return set_error(PSVT_EINVAL, "unknown fault kind");
+        }
+    }
+    s->cv_work.notify_all();
     return PSVT_OK;
 }
 

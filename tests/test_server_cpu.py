@@ -175,3 +175,121 @@ def test_status_flag_rejected_for_served_requests():
     h = ctypes.c_void_p()
     assert psvt.load().psvt_server_create(1 << 30, 4, ctypes.byref(cfg), psvt.SERVER_FAKE,
                                           ctypes.byref(h)) == psvt.PSVT_EINVAL
+
+
+def test_planning_failure_fails_only_its_request():
+    """Fault injection: the 4th admission's plan fails; only that request
+    fails, every other one completes."""
+    srv = psvt.Server(budget_bytes=1 << 30, max_slots=8, fake=True)
+    srv.inject_fault(psvt.FAULT_PLAN, 3)
+    tickets = [submit(srv, 64 + 8 * i, 48) for i in range(10)]
+    srv.drain(timeout=30)
+    states = [srv.poll(t) for t in tickets]
+    assert states[3] == psvt.RQ_FAILED
+    assert all(s == psvt.RQ_DONE for i, s in enumerate(states) if i != 3)
+    st = srv.stats()
+    assert st["failed"] == 1 and st["completed"] == 9 and st["timed_out"] == 0
+    srv.close()
+
+
+def test_launch_failure_fails_its_tick_only():
+    """Fault injection: the first tick fails as a launch error would.  The
+    requests of that tick fail; requests of the other lanes and requests
+    submitted afterwards complete; the workspaces all return to the pool
+    (a budget that holds one large request at a time still serves them)."""
+    srv = psvt.Server(budget_bytes=1 << 30, max_slots=64, fake=True)
+    srv.inject_fault(psvt.FAULT_TICK, 0)
+    small = [submit(srv, 64, 48) for _ in range(3)]
+    with pytest.raises(psvt.PsvtError, match="launch failed"):
+        srv.drain(timeout=30)        # reports the injected launch error ...
+    big = [submit(srv, 2048, 1024), submit(srv, 4096, 2048)]   # other lanes
+    later = [submit(srv, 64, 48) for _ in range(3)]
+    with pytest.raises(psvt.PsvtError):
+        srv.drain(timeout=30)
+    first = [srv.poll(t) for t in small]
+    assert first.count(psvt.RQ_FAILED) >= 1
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in big + later)   # ... which stayed with its tick
+    st = srv.stats()
+    assert st["failed"] == first.count(psvt.RQ_FAILED)
+    assert st["active"] == 0 and st["queued"] == 0
+    srv.close()
+    # one slot of budget: failed requests' workspaces must come back
+    budget = 4 * psvt.workspace_bytes(psvt.OP_SVT, 256, 192, psvt.make_config()[0])
+    srv = psvt.Server(budget_bytes=budget, max_slots=64, fake=True)
+    srv.inject_fault(psvt.FAULT_TICK, 1)
+    ts = [submit(srv, 256, 192) for _ in range(12)]
+    with pytest.raises(psvt.PsvtError):
+        srv.drain(timeout=30)
+    assert all(srv.poll(t) in (psvt.RQ_DONE, psvt.RQ_FAILED) for t in ts)
+    assert srv.stats()["completed"] >= 8
+    srv.close()
+
+
+def test_deadline_fails_stalled_requests_and_frees_their_memory():
+    """Fault injection: fake ticks stall.  With a 0.2 s deadline the running
+    and the queued requests fail (timed_out), their memory returns to the
+    pool, and after the stall clears new requests complete."""
+    budget = 2 * psvt.workspace_bytes(psvt.OP_SVT, 256, 192, psvt.make_config()[0])
+    srv = psvt.Server(budget_bytes=budget, max_slots=8, fake=True)
+    srv.inject_fault(psvt.FAULT_STALL, 1)
+    srv.set_timeout(0.2)
+    ts = [submit(srv, 256, 192) for _ in range(5)]   # two run, three wait for memory
+    t0 = time.time()
+    for t in ts:
+        assert srv.wait(t, timeout=10) == psvt.RQ_FAILED
+    assert time.time() - t0 < 5
+    st = srv.stats()
+    assert st["timed_out"] == 5 and st["failed"] == 5 and st["active"] == 0 and st["queued"] == 0
+    srv.inject_fault(psvt.FAULT_STALL, 0)
+    srv.set_timeout(0)
+    ok = [submit(srv, 256, 192) for _ in range(4)]
+    srv.drain(timeout=30)
+    assert all(srv.poll(t) == psvt.RQ_DONE for t in ok)
+    assert srv.stats()["peak_bytes"] <= budget
+    srv.close()
+
+
+def test_fault_injection_is_for_fake_servers_and_checks_arguments():
+    srv = psvt.Server(budget_bytes=1 << 30, max_slots=4, fake=True)
+    with pytest.raises(psvt.PsvtError):
+        srv.inject_fault(99, 0)
+    with pytest.raises(psvt.PsvtError):
+        srv.set_timeout(-1.0)
+    srv.close()
+
+
+def test_concurrent_clients_with_faults_and_deadlines():
+    """Several client threads submit, poll and wait while ticks fail now and
+    then and a deadline is set: every request ends done or failed, the
+    counters add up, and destroy joins cleanly (also the stress run of the
+    thread-sanitizer build)."""
+    import threading
+    srv = psvt.Server(budget_bytes=1 << 28, max_slots=16, fake=True)
+    srv.inject_fault(psvt.FAULT_TICK, 7)
+    srv.set_timeout(5.0)
+    tickets = []
+    lock = threading.Lock()
+
+    def client(k):
+        for i in range(40):
+            t = submit(srv, 32 + 7 * k + i, 24 + 3 * i)
+            with lock:
+                tickets.append(t)
+            if i % 5 == 0:
+                srv.wait(t, timeout=5)
+            else:
+                srv.poll(t)
+    th = [threading.Thread(target=client, args=(k,)) for k in range(6)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    try:
+        srv.drain(timeout=30)
+    except psvt.PsvtError:
+        pass
+    states = [srv.poll(t) for t in tickets]
+    assert all(s in (psvt.RQ_DONE, psvt.RQ_FAILED) for s in states)
+    st = srv.stats()
+    assert st["completed"] + st["failed"] == len(tickets) == 240
+    srv.close()
