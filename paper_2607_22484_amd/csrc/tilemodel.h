@@ -41,13 +41,24 @@ __host__ __device__ inline double cu_rate(int type) {
                                                                                       : 2516.6e12 / 3.0 / 256.0;
 }
 
-// time ~= (most tiles on one CU) x (overhead + tile flops / (eff x CU rate))
+// Blocks of configuration c that one CU holds at once (its LDS: 160 KB per
+// CU; split bf16 keeps both planes of a k-tile up to 128 x 128).
+__host__ __device__ inline int tile_occ(int type, int c) {
+    if (c >= 3) return 1;
+    if (type == 3) return c == 1 ? 2 : 1;
+    return c == 1 ? 4 : 2;
+}
+
+// The CU with the most tiles, p, does all their flops on its MFMA units, in
+// ceil(p / occ) waves of blocks, each wave paying a start and drain:
+//   time ~= p x tile flops / (eff x CU rate) + ceil(p / occ) x overhead
 __host__ __device__ inline double model_time_us(const TileModelTable &t, int type, int M, int N, int K, int sym,
                                                 int c) {
     const double bm = tile_bm(c);
     const double per_cu = ceil(tile_count(M, N, sym, tile_bm(c)) / 256.0);
+    const double waves = ceil(per_cu / tile_occ(type, c));
     const int k = sym ? 1 : 0;
-    return per_cu * (t.overhead_us[type][k][c] + 1e6 * bm * bm * 2.0 * K / (t.eff[type][k][c] * cu_rate(type)));
+    return per_cu * 1e6 * bm * bm * 2.0 * K / (t.eff[type][k][c] * cu_rate(type)) + waves * t.overhead_us[type][k][c];
 }
 
 __host__ __device__ inline int pick_tile(const TileModelTable &t, int type, int M, int N, int K, int sym) {

@@ -4,11 +4,15 @@ For every tile configuration (64, 128, 192, 256) it times the library's
 product kernel, forced to that configuration, on a set of product shapes of
 the method (symmetric s x s x s and s x s x l products, rectangular l x s x s
 products), and fits, per configuration and kind (symmetric or full), the two
-parameters of the library's cost model
+parameters (efficiency, per-wave overhead) of the library's cost model by
+least squares in relative terms: the CU with the most tiles, p = ceil(tiles
+/ 256), does all their flops on its MFMA units, in ceil(p / occ) waves of
+blocks (occ: blocks per CU of the configuration, from its LDS), each wave
+paying a fixed start and drain:
 
-    time ~= ceil(tiles / 256) * (overhead + tile flops / (eff * CU rate))
+    time ~= p * tile flops / (eff * CU rate) + ceil(p / occ) * overhead
 
-by least squares (time / ceil(tiles/256) is linear in overhead and 1/eff).
+(linear in 1/eff and overhead).
 It writes "id sym eff overhead_us" lines to ``tune_table.txt`` beside the
 library (loaded by the Python binding; C callers use ``psvt_tune_load``) and
 reports, per shape, the configuration the model picks against the fastest
@@ -35,6 +39,38 @@ SHAPES = [  # (M, N, K, sym)
     (4096, 4096, 4096, True), (4096, 4096, 8192, True), (1024, 1024, 1024, False), (2048, 2048, 2048, False),
     (4096, 4096, 4096, False), (8192, 4096, 4096, False),
 ]
+
+
+def tile_occ(dtype, t):
+    """Blocks per CU of configuration t (tilemodel.h: tile_occ)."""
+    if t >= 3:
+        return 1
+    if dtype == 3:
+        return 2 if t == 1 else 1
+    return 4 if t == 1 else 2
+
+
+def per_cu_and_waves(M, N, bm, sym, dtype, t):
+    per_cu = math.ceil(tile_count(M, N, bm, sym) / 256.0)
+    return per_cu, math.ceil(per_cu / tile_occ(dtype, t))
+
+
+def model_us(table, dtype, M, N, K, sym, t):
+    """tilemodel.h: model_time_us."""
+    bm = TILES[t]
+    p, waves = per_cu_and_waves(M, N, bm, sym, dtype, t)
+    e, o = table[(dtype, t, int(sym))]
+    return p * 1e6 * bm * bm * 2.0 * K / (e * CU_RATES[dtype]) + waves * o
+
+
+def model_pick(table, dtype, M, N, K, sym):
+    """tilemodel.h: pick_tile (a configuration must win by 0.1 %)."""
+    best, arg = 1e300, 2
+    for t in TILES:
+        v = model_us(table, dtype, M, N, K, sym, t)
+        if v < best * 0.999:
+            best, arg = v, t
+    return arg
 
 
 def tile_count(M, N, bm, sym):
@@ -80,20 +116,42 @@ def fit(rows):
             for r in rows:
                 if int(r["sym"]) != sym or int(r.get("dtype", 0)) != dt:
                     continue
-                per_cu = math.ceil(tile_count(r["M"], r["N"], bm, r["sym"]) / 256.0)
-                work_us = 1e6 * bm * bm * 2.0 * r["K"] / CU_RATES[dt]
-                X.append([1.0, work_us])
-                y.append(1e6 * r["times"][t] / per_cu)
+                p, waves = per_cu_and_waves(r["M"], r["N"], bm, r["sym"], dt, t)
+                work_us = p * 1e6 * bm * bm * 2.0 * r["K"] / CU_RATES[dt]
+                X.append([waves, work_us])
+                y.append(1e6 * r["times"][t])
             if not X:
                 continue
-            coef, *_ = np.linalg.lstsq(np.array(X), np.array(y), rcond=None)
+            Xa, ya = np.array(X), np.array(y)
+            w = 1.0 / ya  # relative errors: small and large products count alike
+            coef, *_ = np.linalg.lstsq(Xa * w[:, None], ya * w, rcond=None)
             over, inv_eff = float(coef[0]), float(coef[1])
-            if over < 0 or inv_eff < 1.0:  # fall back to a pure-efficiency fit
-                over = max(over, 0.0)
-                inv_eff = max(1.0, float(np.sum((np.array(y) - over) * np.array(X)[:, 1]) /
-                                     np.sum(np.array(X)[:, 1] ** 2)))
-            table[(dt, t, sym)] = (min(1.0, 1.0 / inv_eff), over)
+            if over < 0:  # refit through a zero overhead
+                over = 0.0
+                inv_eff = float(np.sum(w * w * ya * Xa[:, 1]) / np.sum((w * Xa[:, 1]) ** 2))
+            if inv_eff < 1.0 and over > 0:  # an overhead that buys an efficiency above 1: refit without it
+                over = 0.0
+                inv_eff = float(np.sum(w * w * ya * Xa[:, 1]) / np.sum((w * Xa[:, 1]) ** 2))
+            if inv_eff < 1.0:
+                print("warning: dtype %d tile %d sym %d fits an efficiency above 1 (%.3f): clamped"
+                      % (dt, t, sym, 1.0 / inv_eff), flush=True)
+                inv_eff = 1.0
+            table[(dt, t, sym)] = (1.0 / inv_eff, over)
     return table
+
+
+def report_regret(rows, table, pick_of):
+    """Per shape: the configuration picked against the fastest measured;
+    returns the worst time ratio."""
+    worst = 1.0
+    for r in rows:
+        pick = pick_of(r)
+        best = min(r["times"], key=r["times"].get)
+        worst = max(worst, r["times"][pick] / r["times"][best])
+        print("dtype=%d M=%d N=%d K=%d sym=%d: model picks %d (%.3f ms), best %d (%.3f ms)"
+              % (r["dtype"], r["M"], r["N"], r["K"], r["sym"], TILES[pick], r["times"][pick] * 1e3, TILES[best],
+                 r["times"][best] * 1e3), flush=True)
+    return worst
 
 
 def write_table(path, table):
@@ -117,7 +175,8 @@ def main():
             r["times"] = {int(k): v for k, v in r["times"].items()}
         table = fit(rows)
         write_table(args.out, table)
-        print(table)
+        print("max regret %.3f" % report_regret(rows, table, lambda r: model_pick(table, r["dtype"], r["M"], r["N"],
+                                                                                 r["K"], r["sym"])))
         return 0
     import torch
     import paper_2607_22484_amd as psvt
@@ -128,8 +187,8 @@ def main():
             times = {}
             for t, bm in TILES.items():
                 sec = measure(psvt, torch, M, N, K, sym, t, dt)
-                per_cu = math.ceil(tile_count(M, N, bm, sym) / 256.0)
-                eff = per_cu * bm * bm * 2.0 * K / (sec * CU_RATES[dt])
+                p, _ = per_cu_and_waves(M, N, bm, sym, dt, t)
+                eff = p * bm * bm * 2.0 * K / (sec * CU_RATES[dt])
                 times[t] = sec
                 useful = (M * (M + 1) * K if sym else 2.0 * M * N * K) / sec / 1e12
                 print("dtype=%d M=%d N=%d K=%d sym=%d tile=%d: %.3f ms, %.1f useful TF/s, model eff %.3f"
@@ -140,15 +199,8 @@ def main():
     write_table(out, table)
     lib = psvt.load()
     lib.psvt_tune_load(out.encode())
-    regret = []
-    for r in rows:
-        pick = psvt.pick_tile(r["M"], r["N"], r["K"], r["sym"], r["dtype"])
-        best = min(r["times"], key=r["times"].get)
-        regret.append(r["times"][pick] / r["times"][best])
-        print("dtype=%d M=%d N=%d K=%d sym=%d: model picks %d (%.3f ms), best %d (%.3f ms)"
-              % (r["dtype"], r["M"], r["N"], r["K"], r["sym"], TILES[pick], r["times"][pick] * 1e3, TILES[best],
-                 r["times"][best] * 1e3), flush=True)
-    print("table:", table, "max regret %.3f" % max(regret), flush=True)
+    worst = report_regret(rows, table, lambda r: psvt.pick_tile(r["M"], r["N"], r["K"], r["sym"], r["dtype"]))
+    print("table:", table, "max regret %.3f" % worst, flush=True)
     if args.json:
         with open(args.json, "w") as f:
             json.dump(dict(table={"%d_%d_%d" % k: v for k, v in table.items()}, rows=rows), f)

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2607_22484_amd as psvt
@@ -286,3 +287,29 @@ def test_batched_device_descriptors_validate():
                 assert rc == psvt.PSVT_EINVAL   # the H-form needs the polar factor: svt only
             else:
                 assert rc == psvt.PSVT_EWORKSPACE, (kw, lib.psvt_last_error())
+
+
+def test_tune_model_replica_matches_library_picks():
+    """The tuner's replica of the cost model (used to refit and report
+    regret off the device) picks what the library picks for the committed
+    table, over random product shapes of every operand type; the committed
+    table has no efficiency clamped at 1."""
+    from paper_2607_22484_amd import tune
+    lib = psvt.load()
+    assert lib.psvt_tune_load(psvt.TUNE_TABLE.encode()) == psvt.PSVT_OK
+    table = {}
+    with open(psvt.TUNE_TABLE) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if line:
+                dt, t, sym, e, o = int(line[0]), int(line[1]), int(line[2]), float(line[3]), float(line[4])
+                table[(dt, t, sym)] = (e, o)
+    assert len(table) == 32 and all(0.0 < e < 1.0 for e, _ in table.values())
+    rng = np.random.default_rng(7)
+    for _ in range(400):
+        dt = int(rng.integers(0, 4))
+        sym = bool(rng.integers(0, 2))
+        M = int(rng.integers(1, 9000))
+        N = M if sym else int(rng.integers(1, 9000))
+        K = int(rng.integers(1, 9000))
+        assert psvt.pick_tile(M, N, K, sym, dt) == tune.model_pick(table, dt, M, N, K, sym), (dt, M, N, K, sym)
