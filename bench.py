@@ -661,6 +661,49 @@ def loop_leg(psvt, torch, dev, checks, rates=(100, 200, 500, 1000, 2000, 5000), 
     return out
 
 
+def gram_leg(psvt, torch, dev, checks, shapes=((16384, 1024, 100), (1024, 16384, 100), (8192, 1024, 100))):
+    """Gram form of the polar factor (PSVT_FLAG_GRAM) against the standard
+    form, l >> s: rank-r signal (sigma in [1, 10]) plus noise, tau twice the
+    noise's spectral norm; time per SVT with FP32 and with the 18 BF16 + 2
+    FP32 sign schedule (the Gram form's P products are FP32 either way),
+    errors against the certified oracle."""
+    from paper_2607_22484_amd import inputs
+    out = {}
+    for (m, n, r) in shapes:
+        pb = inputs.noisy_lowrank(m, n, rank=r, idx=7, norm_iters=60)
+        A = torch.from_numpy(pb.A).to(dev)
+        Y = torch.empty_like(A)
+        row = {"rank": r, "tau": pb.tau}
+        for name, kw in [("fp32", dict()), ("fp32_gram", dict(flags=psvt.FLAG_GRAM)),
+                         ("bf16S", dict(n_bf16=18)), ("bf16S_gram", dict(n_bf16=18, flags=psvt.FLAG_GRAM))]:
+            cfg, _ = psvt.make_config(iters=20, **kw)
+            ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, m, n, cfg), dtype=torch.uint8, device=dev)
+            ms = time_calls(torch, lambda: psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw), 3)
+            row[name] = {"ms": ms}
+            if checks is not None:
+                Yh = Y.cpu().numpy().astype(np.float64)
+
+                def check(oracle, pb=pb, Yh=Yh, dst=row[name], r=r, memo={}):
+                    key = pb.name
+                    if key not in memo:
+                        memo.clear()
+                        memo[key] = oracle.svt_gapped(pb.A.astype(np.float64), pb.tau, k=r + 64, return_bound=True)
+                    ref, cert = memo[key]
+                    dst["rel_err"] = oracle.rel_fro_err(Yh, ref)
+                    dst["reference_certified_to"] = cert
+                checks.append(check)
+            del ws
+        row["gram_speedup_fp32"] = row["fp32"]["ms"] / row["fp32_gram"]["ms"]
+        row["gram_speedup_bf16S"] = row["bf16S"]["ms"] / row["bf16S_gram"]["ms"]
+        out["%dx%d" % (m, n)] = row
+        print("[bench] gram %dx%d: fp32 %.2f ms, gram %.2f ms; bf16S %.2f ms, gram %.2f ms"
+              % (m, n, row["fp32"]["ms"], row["fp32_gram"]["ms"], row["bf16S"]["ms"], row["bf16S_gram"]["ms"]),
+              file=sys.stderr, flush=True)
+        del A, Y
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -673,9 +716,9 @@ def main():
                     help="size of the matrix the CPU oracle is timed on (the main workload's size: one of its "
                          "own matrices)")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving legs")
-    ap.add_argument("--forms", default="small,rank,precision,batched,serving,loops,fig1,fig2",
-                    help="comma-separated subset of the small / rank / precision / batched / serving / loops / fig1 "
-                         "/ fig2 legs")
+    ap.add_argument("--forms", default="small,rank,precision,batched,serving,loops,gram,fig1,fig2",
+                    help="comma-separated subset of the small / rank / precision / batched / serving / loops / gram "
+                         "/ fig1 / fig2 legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB elementwise copy first (scale reference for PMC byte counters)")
     args = ap.parse_args()
@@ -801,6 +844,9 @@ def main():
             print("[bench] serving form ...", file=sys.stderr, flush=True)
             forms["serving"] = serving_leg(psvt, torch, dev, checks)
             torch.cuda.empty_cache()
+        if "gram" in want:
+            print("[bench] Gram form of P, l >> s ...", file=sys.stderr, flush=True)
+            forms["gram_form"] = gram_leg(psvt, torch, dev, checks)
         if "loops" in want:
             print("[bench] serving form driven by completion loops ...", file=sys.stderr, flush=True)
             forms["serving_loops"] = loop_leg(psvt, torch, dev, checks)

@@ -128,6 +128,21 @@ enum { PSVT_OP_SVT = 0, PSVT_OP_POLAR = 1, PSVT_OP_POLAR_SYM = 2, PSVT_OP_RANK_R
 /* psvt_svt_batched / psvt_rank_r_batched only: run the batch as ONE
  * persistent launch (below); PSVT_EINVAL elsewhere. */
 #define PSVT_FLAG_PERSISTENT 0x20u
+/* svt only: the polar factor in Gram form (for l >> s).  With T = X^T X,
+ * every polar iterate is X N_k for a polynomial N_k in T, so the iteration
+ * runs on s x s matrices only (Q = p(Y), N <- N Q, Y <- Y Q^2, on
+ * Y0 = Pi T Pi / theta^2 + I - Pi with Pi = (I + S)/2 from the sign
+ * iterations, which run first: the directions Pi removes are set to 1, so
+ * N stays below sigma_max / tau; four s x s products per iteration, each
+ * symmetrised, or 8 s^3 flops against 3 l s^2 + s^3 on the l x s iterate:
+ * it pays for l >= 3 s), and A_tau = X (nu I - tau T^{-1/2}) (I + S)/2
+ * takes one s x s and one l x s x s product (proof of Proposition 1:
+ * A - tau P = A (I - tau (A^T A)^{-1/2})).  The P-side products are FP32
+ * whatever the schedule (S follows it).  T squares the condition number of
+ * the kept part: the error grows with sigma_max / tau (simulated in FP32:
+ * about 3e-8 for low rank plus noise; 2e-6 to 1.3e-4 for log-spaced
+ * spectra with sigma_max / tau from 3 to 4000).  Excludes PSVT_FLAG_HFORM. */
+#define PSVT_FLAG_GRAM 0x40u
 
 #define PSVT_STATUS_NONFINITE_INPUT 0x1u
 #define PSVT_STATUS_NONFINITE_OUTPUT 0x2u

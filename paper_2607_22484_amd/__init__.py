@@ -27,7 +27,7 @@ OP_SVT, OP_POLAR, OP_POLAR_SYM, OP_RANK_R = 0, 1, 2, 3
 SIDE_AUTO, SIDE_RIGHT, SIDE_LEFT = 0, 1, 2
 DTYPE_F32, DTYPE_BF16, DTYPE_FP8, DTYPE_BF16X3 = 0, 1, 2, 3
 FLAG_PLAIN_S, FLAG_SPLIT_P, FLAG_PLAIN_P, FLAG_STATUS, FLAG_HFORM = 0x1, 0x2, 0x4, 0x8, 0x10
-FLAG_PERSISTENT = 0x20
+FLAG_PERSISTENT, FLAG_GRAM = 0x20, 0x40
 STATUS_NONFINITE_INPUT, STATUS_NONFINITE_OUTPUT, STATUS_NOT_CONVERGED, STATUS_INVALID = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [

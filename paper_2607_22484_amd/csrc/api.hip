@@ -124,13 +124,15 @@ int read_cfg(const psvt_config *c, Cfg &out) {
                     out.iters);
     if (c->side < 0 || c->side > 2) return fail(PSVT_EINVAL, "side = %d", c->side);
     const uint32_t known = PSVT_FLAG_SPLIT_P | PSVT_FLAG_PLAIN_S | PSVT_FLAG_PLAIN_P | PSVT_FLAG_STATUS | PSVT_FLAG_HFORM |
-                           PSVT_FLAG_PERSISTENT;
+                           PSVT_FLAG_PERSISTENT | PSVT_FLAG_GRAM;
     if (c->flags & ~known) return fail(PSVT_EINVAL, "unknown flags 0x%x", c->flags);
     // the batched entry points take this flag off before they get here
     if (c->flags & PSVT_FLAG_PERSISTENT)
         return fail(PSVT_EINVAL, "PSVT_FLAG_PERSISTENT applies to psvt_svt_batched / psvt_rank_r_batched only");
     if ((c->flags & PSVT_FLAG_SPLIT_P) && (c->flags & PSVT_FLAG_PLAIN_P))
         return fail(PSVT_EINVAL, "PSVT_FLAG_SPLIT_P and PSVT_FLAG_PLAIN_P exclude each other");
+    if ((c->flags & PSVT_FLAG_GRAM) && (c->flags & PSVT_FLAG_HFORM))
+        return fail(PSVT_EINVAL, "PSVT_FLAG_GRAM and PSVT_FLAG_HFORM exclude each other");
     if (c->norm_safety != 0.0 && !(c->norm_safety >= 1.0 && c->norm_safety <= 16.0))
         return fail(PSVT_EINVAL, "norm_safety = %g outside [1, 16]", c->norm_safety);
     if (c->norm_safety != 0.0) out.safety = c->norm_safety;
@@ -774,6 +776,136 @@ int final_product(const Layout &L, void *ws, const float *P, double tau, const f
     return PSVT_OK;
 }
 
+// Gram form of the polar factor (PSVT_FLAG_GRAM).  With T = X0^T X0 and
+// Y0 = T / theta_P^2, every polar iterate is X_k = X0 N_k / theta_P with N_k
+// a polynomial in T, and its Gram matrix Y_k = N_k Y0 N_k is one too; the
+// odd-quintic step X <- X p(X^T X), p(y) = a + b y + c y^2, becomes
+//   Q = p(Y_k),  N_{k+1} = N_k Q,  Y_{k+1} = Y_k Q^2
+// (N_0 = I, so N_1 = p(Y0) and Y_1 = Y0 N_1^2): s x s products only, FP32.
+// N_K tends to Y0^{-1/2}, so P = X0 T^{-1/2} = X0 N_K / theta_P.
+// Only the directions that Pi = (I + S)/2 keeps matter, so the iteration
+// runs on Y0' = Pi Y0 Pi + (I - Pi): the same on those directions, 1 on the
+// others (which Pi removes again at the end).  Its spectrum lies in
+// [tau^2 / theta_P^2, 1] instead of reaching down to the smallest singular
+// value: N stays below theta_P / tau instead of growing like the inverse of
+// the smallest one, which is what keeps the FP32 iteration stable.  The
+// matrices are symmetric in exact arithmetic; each product is taken in full
+// and symmetrised as (C + C^T) / 2, since the iteration amplifies an
+// antisymmetric rounding part (keeping one triangle is not enough).
+// Buffers: Y0' over T, Q in Bm, Pi Y0 and Y Q in Xp, Y in BS, N in Xq / X2,
+// the unsymmetrised products in H (the S-side buffers other than Pi's are
+// free once the sign iterations are done).
+int gram_step(const float *A, const float *B, const float *D, float alpha, int i_alpha, float beta, int i_beta,
+              float diag, float *dst, float *tmp, const Layout &L, const Scalars *sc, Exec &ex, const char *what) {
+    GemmArgs g = gemm_defaults();
+    g.A = A;
+    g.B = B;
+    g.lda = g.ldb = L.ldS;
+    g.D = D;
+    g.ldd = D ? L.ldS : 0;
+    g.C = tmp;
+    g.ldc = L.ldS;
+    g.M = g.N = g.K = (int)L.s;
+    g.alpha = alpha;
+    g.i_alpha = i_alpha;
+    g.beta = beta;
+    g.i_beta = i_beta;
+    g.diag = diag;
+    g.sc = sc;
+    HIP_TRY(ex.gemm(g, OP_F32, what), what);
+    TileOp op = make_symmetrize_scale(tmp, L.s, L.ldS, dst, L.ldS, sc);
+    op.i_scale = -1;  // (C + C^T) / 2, no scaling
+    HIP_TRY(ex.tile(op, what), what);
+    return PSVT_OK;
+}
+
+int gram_polar(const Cfg &c, const Layout &L, void *ws, const float *Pi, Exec &ex, const float **out_N) {
+    const Scalars *sc = (const Scalars *)at(ws, L.scal);
+    float *T = F(ws, L.T);
+    float *Q = F(ws, L.Bm), *W = F(ws, L.Xp), *Y = F(ws, L.BS), *tmp = F(ws, L.H);
+    float *Nb[2] = {F(ws, L.Xq), F(ws, L.X2)};
+    // Y0' = Pi Y0 Pi + (I - Pi): W = Pi T / theta^2, then W Pi - Pi + I into T
+    GemmArgs g = gemm_defaults();
+    g.A = Pi;
+    g.B = T;
+    g.lda = g.ldb = L.ldS;
+    g.C = W;
+    g.ldc = L.ldS;
+    g.M = g.N = g.K = (int)L.s;
+    g.i_alpha = F_P2;
+    g.sc = sc;
+    HIP_TRY(ex.gemm(g, OP_F32, "gram Pi Y0"), "gram Pi Y0");
+    int rc;
+    if ((rc = gram_step(W, Pi, Pi, 1.0f, -1, -1.0f, -1, 1.0f, T, tmp, L, sc, ex, "gram Y0"))) return rc;
+    const int K = c.iters;
+    int cur = 0;
+    for (int t = 0; t < K; ++t) {
+        float a, b, cc;
+        coef(c, t, a, b, cc);
+        const float *Yt = t == 0 ? T : Y;
+        if (t == 0) {  // N_1 = p(Y0')
+            if ((rc = gram_step(T, T, T, cc, -1, b, -1, a, Nb[0], tmp, L, sc, ex, "gram N"))) return rc;
+        } else {
+            if ((rc = gram_step(Y, Y, Y, cc, -1, b, -1, a, Q, tmp, L, sc, ex, "gram Q"))) return rc;
+            if ((rc = gram_step(Nb[cur], Q, nullptr, 1.0f, -1, 0.0f, -1, 0.0f, Nb[cur ^ 1], tmp, L, sc, ex, "gram N")))
+                return rc;
+            cur ^= 1;
+        }
+        if (t + 1 < K) {  // Y <- Y Q Q  (t = 0: Y0' N_1 N_1)
+            const float *Qt = t == 0 ? Nb[0] : Q;
+            if ((rc = gram_step(Yt, Qt, nullptr, 1.0f, -1, 0.0f, -1, 0.0f, W, tmp, L, sc, ex, "gram Y Q"))) return rc;
+            if ((rc = gram_step(W, Qt, nullptr, 1.0f, -1, 0.0f, -1, 0.0f, Y, tmp, L, sc, ex, "gram Y"))) return rc;
+        }
+    }
+    *out_N = Nb[cur];
+    return PSVT_OK;
+}
+
+// Final product of the Gram form: A - tau P = X0 (nu I - (tau / theta_P) N),
+// so A_tau = X0 F with F = (nu I - (tau / theta_P) N) Pi.  The product takes
+// F^T = nu Pi - (tau / theta_P) Pi N (one s x s product, into Xp) as the
+// rows of its NT operand, then Y = X0 F (transposed for the left side).
+// Both weights come from the scalar block (nu, and tau / theta_P written by
+// the theta_P pass), so the stage does not depend on tau itself.
+int gram_final(const Layout &L, void *ws, const float *N, double tau, const float *Pi, float *Y, int64_t ldy,
+               Exec &ex) {
+    Scalars *sc = (Scalars *)at(ws, L.scal);
+    float *Ft = F(ws, L.Xp);
+    GemmArgs g = gemm_defaults();
+    g.A = Pi;
+    g.B = N;
+    g.lda = g.ldb = L.ldS;
+    g.D = Pi;
+    g.ldd = L.ldS;
+    g.C = Ft;
+    g.ldc = L.ldS;
+    g.M = g.N = g.K = (int)L.s;
+    g.alpha = -1.0f;
+    g.i_alpha = F_TAU_P;
+    g.beta = 1.0f;
+    g.i_beta = F_NU;
+    g.sc = sc;
+    HIP_TRY(ex.gemm(g, OP_F32, "gram F"), "gram F");
+    GemmArgs h = gemm_defaults();
+    h.A = F(ws, L.X0);
+    h.lda = L.ldS;
+    h.B = Ft;
+    h.ldb = L.ldS;
+    h.M = (int)L.l;
+    h.N = (int)L.s;
+    h.K = (int)L.s;
+    h.sc = sc;
+    if (L.right) {
+        h.C = Y;
+        h.ldc = ldy;
+    } else {
+        h.CT = Y;
+        h.ldct = ldy;
+    }
+    HIP_TRY(ex.gemm(h, OP_F32, "final product"), "final product");
+    return PSVT_OK;
+}
+
 // Warm-start buffers: s x s with row stride ld_pi, outside the workspace.
 int check_warm(const Cfg &c, const Layout &L, const void *ws) {
     if (!c.warm_pi && !c.pi_out) return PSVT_OK;
@@ -833,6 +965,20 @@ int plan_svt_like(int op, const float *A, int64_t m, int64_t n, int64_t lda, dou
         return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only (it needs the polar factor)");
     if ((c.flags & PSVT_FLAG_HFORM) && c.n_fp8 > 0)
         return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM takes S from P^T A: P's e4m3 iterations are too coarse for it");
+    if (c.flags & PSVT_FLAG_GRAM) {  // S as usual, then P in Gram form: s x s products only
+        if (op != PSVT_OP_SVT) return fail(PSVT_EINVAL, "PSVT_FLAG_GRAM applies to svt only");
+        const float *N = nullptr, *Pi = nullptr;
+        if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, true, c.safety))) return rc;
+        if ((rc = shifted_gram(L, ws, ex, c.safety))) return rc;
+        if (ex.rec) {
+            ex.cut[0] = ex.cut[1] = ex.cut[2] = ex.rec->size();
+            ex.chains = false;
+        }
+        if ((rc = sign_iterations(c, L, ws, ex, true, nullptr, 0, &Pi))) return rc;
+        if ((rc = gram_polar(c, L, ws, Pi, ex, &N))) return rc;
+        if ((rc = gram_final(L, ws, N, tau, Pi, Y, ldy, ex))) return rc;
+        return status_stages(c, L, ws, ex, Pi, L.ldS, true, Y, m, n, ldy);
+    }
     if (c.flags & PSVT_FLAG_HFORM) {  // P first, then S from P^T A (no concurrent chains)
         const float *P = nullptr, *PT = nullptr, *Pi = nullptr;
         if ((rc = prelude(A, m, n, lda, tau, L, ws, ex, true, c.safety))) return rc;
@@ -1048,7 +1194,8 @@ int psvt_polar(const float *A, int64_t m, int64_t n, int64_t lda, float *P, int6
     Cfg c;
     int rc = read_cfg(cfg, c);
     if (rc) return rc;
-    if (c.flags & PSVT_FLAG_HFORM) return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only");
+    if (c.flags & (PSVT_FLAG_HFORM | PSVT_FLAG_GRAM))
+        return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM and PSVT_FLAG_GRAM apply to svt only");
     if ((rc = check_matrix(A, m, n, lda, "A"))) return rc;
     if ((rc = check_matrix(P, m, n, ldp, "P"))) return rc;
     if (m == 0 || n == 0) return PSVT_OK;
@@ -1071,7 +1218,8 @@ int psvt_polar_sym(const float *G, int64_t n, int64_t ldg, float *S, int64_t lds
     Cfg c;
     int rc = read_cfg(cfg, c);
     if (rc) return rc;
-    if (c.flags & PSVT_FLAG_HFORM) return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM applies to svt only");
+    if (c.flags & (PSVT_FLAG_HFORM | PSVT_FLAG_GRAM))
+        return fail(PSVT_EINVAL, "PSVT_FLAG_HFORM and PSVT_FLAG_GRAM apply to svt only");
     if (c.warm_pi || c.pi_out) return fail(PSVT_EINVAL, "warm starts apply to svt and rank_r");
     if ((rc = check_matrix(G, n, n, ldg, "G"))) return rc;
     if ((rc = check_matrix(S, n, n, lds, "S"))) return rc;

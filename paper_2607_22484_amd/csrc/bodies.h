@@ -61,6 +61,8 @@ __device__ __forceinline__ void fro_final_body(const NormOp &op, double *red) {
         sc->f[base] = (float)it;
         sc->f[base + 1] = (float)(it * it);
         sc->f[base + 2] = (float)(it * it * it * it);
+        // tau / theta_P, tau in the input's units (D_TAU = tau / nu)
+        if (op.mode == NORM_THETA_P) sc->f[F_TAU_P] = (float)(sc->d[D_TAU] * sc->d[D_NU] * it);
     } else if (op.mode == NORM_CONV) {
         sc->d[D_CONV] = op.scale * nrm / sqrt((double)(op.rows > 0 ? op.rows : 1));
     } else if (op.mode == NORM_STATUS) {

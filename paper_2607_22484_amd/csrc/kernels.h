@@ -18,6 +18,7 @@ enum ScalarIdx {
     F_S1 = 5,      // 1 / theta_S, theta_S = sqrt(||H^2||_F) >= |lambda|_max(H)
     F_S2 = 6,
     F_S4 = 7,
+    F_TAU_P = 8,   // tau / theta_P (tau in the input's units): the Gram form's weight of N
     F_COUNT = 16
 };
 // double part

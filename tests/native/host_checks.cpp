@@ -49,7 +49,7 @@ int main() {
     {
         psvt_config c{};
         size_t b = 0;
-        c.flags = 0x40;
+        c.flags = 0x80;
         EXPECT(psvt_workspace_bytes(0, 10, 10, &c, &b) == PSVT_EINVAL);
         c.flags = PSVT_FLAG_PERSISTENT;
         EXPECT(psvt_workspace_bytes(0, 10, 10, &c, &b) == PSVT_EINVAL);

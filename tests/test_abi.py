@@ -109,7 +109,7 @@ def test_config_validation():
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
     cfg, keep = psvt.make_config(iters=2, coeffs=[1.0, 0.0, float("nan"), 1, 0, 0])
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
-    cfg, _ = psvt.make_config(flags=0x40)            # unknown flag
+    cfg, _ = psvt.make_config(flags=0x80)            # unknown flag
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
     cfg, _ = psvt.make_config(flags=psvt.FLAG_SPLIT_P | psvt.FLAG_PLAIN_P)
     assert call_svt(cfg=cfg) == psvt.PSVT_EINVAL
