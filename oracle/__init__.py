@@ -143,6 +143,21 @@ def rank_r(A, tau, nthreads: int = 0):
     return (U * keep) @ V.T
 
 
+def _gram_lambda_max_upper(F):
+    """An upper bound on lambda_max(F^T F) = ||F||_2^2: LAPACK's largest
+    eigenvalue of the computed Gram matrix C (the smaller of F^T F, F F^T)
+    plus n u ||C||_F (the computed eigenvalues are those of C plus a
+    perturbation of norm of order u ||C||_2; Weyl's inequality) plus
+    l u ||F||_F^2 (rounding of the l-term sums that form C)."""
+    C = F.T @ F if F.shape[0] >= F.shape[1] else F @ F.T
+    nc = C.shape[0]
+    if nc == 0:
+        return 0.0
+    u = float(np.finfo(np.float64).eps)
+    return (max(float(np.linalg.eigvalsh(C)[-1]), 0.0) + nc * u * float(np.linalg.norm(C)) +
+            max(F.shape) * u * float(np.sum(F * F)))
+
+
 def prox_error_bound(A, Y, tau, factor=None):
     """Certified upper bound on ||Y - A_tau||_F for any candidate Y.
 
@@ -166,8 +181,9 @@ def prox_error_bound(A, Y, tau, factor=None):
         lambda_max(M^T M) <= lambda_max([[alpha, beta], [beta, gamma]]),
         alpha = lambda_max(W^T M^T M W)          (small eigenproblem)
         beta  = ||W^T M^T M W_perp||_2            (small SVD)
-        gamma = lambda_max(W_perp^T M^T M W_perp) <= ||C^8||_F^(1/8),
-                C = (M W_perp)^T (M W_perp)      (any power bounds it),
+        gamma = lambda_max(W_perp^T M^T M W_perp) = ||M W_perp W_perp^T||_2^2,
+        each computed by LAPACK and raised by a bound on its rounding
+        error (alpha: an SVD of M W; gamma: ``_gram_lambda_max_upper``),
 
     since x^T K x <= alpha |a|^2 + 2 beta |a||b| + gamma |b|^2 for
     x = W a + W_perp b.  It is tight when W spans the top right singular
@@ -191,21 +207,22 @@ def prox_error_bound(A, Y, tau, factor=None):
         nuc = math.sqrt(1.0 + e) * float(sy.sum())
     keep = sy > sy[0] * 1e-13 if sy.size and sy[0] > 0 else np.zeros(sy.shape, bool)
     W = Vyt[keep].T
+    u = float(np.finfo(np.float64).eps)
     if W.shape[1]:
         W, _ = np.linalg.qr(W)
         MW = M @ W
-        alpha = float(np.linalg.eigvalsh(MW.T @ MW)[-1])
+        # ||M W||_2 by an SVD of M W itself (backward stable: relative error
+        # of order max(m, k) u, no rounding of a Gram product)
+        alpha = (float(np.linalg.norm(MW, 2)) * (1.0 + max(MW.shape) * u)) ** 2
         G = MW.T @ M
-        beta = float(np.linalg.norm(G - (G @ W) @ W.T, 2))
+        B = G - (G @ W) @ W.T
+        beta = float(np.linalg.norm(B, 2)) + u * (min(B.shape) * max(B.shape) * float(np.linalg.norm(B)) +
+                                                  m * float(np.linalg.norm(MW)) * float(np.linalg.norm(M)))
         X = M - MW @ W.T
     else:
         alpha = beta = 0.0
         X = M
-    C = X.T @ X if X.shape[0] >= X.shape[1] else X @ X.T
-    for _ in range(3):
-        C = C @ C
-    fro = float(np.linalg.norm(C))
-    gamma = (fro ** 0.125) * (1.0 + 1e-6) if fro > 0 else 0.0
+    gamma = _gram_lambda_max_upper(X)
     lam = 0.5 * (alpha + gamma) + math.sqrt(0.25 * (alpha - gamma) ** 2 + beta * beta)
     spec_up = math.sqrt(max(lam, 0.0)) * (1.0 + 1e-13)
     c = 1.0 if spec_up <= tau else tau / spec_up

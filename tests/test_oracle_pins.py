@@ -350,6 +350,28 @@ def test_certificate_rejects_partial_subspace():
         assert bound > 1e-6 * np.linalg.norm(Y)                       # rejected
 
 
+def test_certificate_with_values_just_below_tau():
+    """Completion iterates keep singular values within a fraction of a
+    percent below tau outside the retained subspace: the certificate must
+    still reach the compressed result's accuracy there (its spectral-norm
+    bound on the complement is that block's norm, not a power-mean that
+    counts the values near tau), and the certified compressed route must
+    equal the full Jacobi oracle."""
+    rng = np.random.default_rng(17)
+    m, n, tau = 300, 150, 2.0
+    U = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    sig = np.concatenate([np.linspace(8.0, 2.2, 20), tau * np.array([0.999, 0.998, 0.997, 0.996, 0.995]),
+                          np.linspace(0.9, 0.01, n - 25)])
+    A = (U * sig) @ V.T
+    # the certificate's floor: sqrt(2 delta tau ||Y||_*) / ||Y||_F for the
+    # relative rounding margin delta ~ 1e-13 of its spectral-norm bound
+    Y, bound = oracle.svt_gapped(A, tau, k=40, power_iters=10, max_rel_bound=2e-6, return_bound=True)
+    assert bound < 2e-6
+    assert relerr(Y, oracle.svt(A, tau)) < 1e-10
+    assert relerr(Y, oracle.svt_from_svd(U, sig, V, tau)) < 1e-10
+
+
 @pytest.mark.parametrize("kind", ["exact", "scaled", "dense_noise", "low_rank", "dropped_term", "transposed"])
 def test_prox_error_bound_is_an_upper_bound(kind):
     """The certificate is an upper bound on ||Y - A_tau||_F for any Y, and
