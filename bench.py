@@ -111,8 +111,13 @@ def cpu_baseline_leg(problems, results, n_sample, checks):
         err = np.linalg.norm(Y - ref)
         delta = float(np.linalg.norm(pb.A.astype(np.float64) - pb.A64))  # prox is 1-Lipschitz
         errs[pb.name] = {"rel_err": float(err / nref), "rel_err_bound_fp32_input": float((err + delta) / (nref - delta))}
+    failures = []
     for check in checks:
-        check(oracle)
+        try:
+            check(oracle)
+        except Exception as e:  # one failed accuracy check must not lose the rest of the line
+            failures.append("%s: %s" % (getattr(check, "__qualname__", "check"), e))
+            print("[bench] accuracy check failed: %s" % failures[-1], file=sys.stderr, flush=True)
     n_main = problems[0].A.shape[0]
     if n_sample >= n_main:
         sample = problems[len(problems) // 2]   # the main workload's own tau = q50 matrix
@@ -129,7 +134,7 @@ def cpu_baseline_leg(problems, results, n_sample, checks):
                                                                        n_main)
     cpu = {"value": 1.0 / (dt * scale), "unit": "matrices/s", "cores": oracle.threads(), "kind": "oracle",
            "sample": what}
-    return cpu, errs
+    return cpu, errs, failures
 
 
 def time_calls(torch, fn, reps):
@@ -548,6 +553,30 @@ def serving_leg(psvt, torch, dev, checks, rates=(100, 200, 500, 1000, 2000, 5000
     return out
 
 
+def _completion_reference(oracle, G, tau, r):
+    """Reference thresholding of one completion iterate: the certified
+    compressed oracle with k = r + 64, then with a wider basis and more power
+    iterations; below 1300 on the short side the full Jacobi SVD when neither
+    certifies to 1e-4.  Returns (reference, certified relative bound or 0 for
+    the full SVD or None when uncertified, how)."""
+    s = min(G.shape)
+    for k, q in ((r + 64, 10), (min(s, 2 * r + 256), 16)):
+        try:
+            ref, cert = oracle.svt_gapped(G, tau, k=k, power_iters=q, max_rel_bound=1e-4, return_bound=True)
+            return ref, cert, "compressed k=%d" % k
+        except RuntimeError as e:
+            print("[bench] completion reference %dx%d, k=%d: %s" % (G.shape + (k, e)), file=sys.stderr, flush=True)
+    if s <= 1300:
+        sv = np.linalg.svd(G.astype(np.float64), compute_uv=False)
+        print("[bench] completion iterate %dx%d: %d singular values above tau=%.4g; next %s"
+              % (G.shape + (int((sv > tau).sum()), tau, np.array2string(sv[(sv > tau).sum():][:4], precision=4))),
+              file=sys.stderr, flush=True)
+        return oracle.svt(G, tau), 0.0, "full Jacobi SVD"
+    ref, cert = oracle.svt_gapped(G, tau, k=min(s, 2 * r + 256), power_iters=16, max_rel_bound=float("inf"),
+                                  return_bound=True)
+    return ref, None, "compressed, uncertified (bound %.3g)" % cert
+
+
 def loop_leg(psvt, torch, dev, checks, rates=(100, 200, 500, 1000, 2000, 5000), count=2000, steps=20,
              lp=(("n_bf16", 18),)):
     """Serving form driven by matrix-completion proximal loops (section 2:
@@ -647,12 +676,10 @@ def loop_leg(psvt, torch, dev, checks, rates=(100, 200, 500, 1000, 2000, 5000), 
         def check(oracle, dst=out):
             rows = []
             for (i, k), (G, Y, tau, shape, r, w) in sorted(kept.items()):
-                # completion iterates carry signal values close to tau, which
-                # loosens the certificate; 1e-4 is far inside the 1e-2 checked
-                ref, cert = oracle.svt_gapped(G, tau, k=r + 64, power_iters=10, max_rel_bound=1e-4,
-                                              return_bound=True)
+                ref, cert, how = _completion_reference(oracle, G, tau, r)
                 rows.append({"loop": i, "step": k, "shape": list(shape), "rank": r, "warm": w,
-                             "rel_err": oracle.rel_fro_err(Y, ref), "reference_certified_to": cert})
+                             "rel_err": oracle.rel_fro_err(Y, ref), "reference_certified_to": cert,
+                             "reference": how})
             dst["sampled_step_errors"] = rows
             dst["worst_sampled_rel_err"] = max(x["rel_err"] for x in rows)
             warm_errs = [x["rel_err"] for x in rows if x["warm"]]
@@ -860,9 +887,10 @@ def main():
         out["forms"] = forms
     if not args.no_cpu:
         print("[bench] cpu oracle leg (baseline timing and every accuracy figure) ...", file=sys.stderr, flush=True)
-        cpu, errs = cpu_baseline_leg(problems, res, args.cpu_sample, checks)
+        cpu, errs, failures = cpu_baseline_leg(problems, res, args.cpu_sample, checks)
         out["cpu_baseline"] = cpu
         out["accuracy"] = errs
+        out["accuracy_check_failures"] = failures
         out["rel_err_max"] = max(e["rel_err_bound_fp32_input"] for e in errs.values())
     print(json.dumps(out), flush=True)
 
