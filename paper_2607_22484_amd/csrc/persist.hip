@@ -123,25 +123,31 @@ extern __shared__ __attribute__((aligned(16))) uint8_t persist_lds[];
 template <int ET, int BM>
 __device__ __forceinline__ void gemm_item(const GemmArgs &g, bool two_a, int item, uint8_t *smem) {
     int bi, bj;
+    floatx16 acc[BM / 64][BM / 64];
     if (g.sym) {
         tile_coords<true>(item, g.M, g.N, BM, BM, bi, bj);
         if (g.direct)
-            gemm_tile_direct<ET, BM, BM, true>(g, bi, bj, smem);
+            gemm_tile_direct<ET, BM, BM, true>(g, bi, bj, smem, acc);
         else
-            gemm_tile<ET, BM, BM, false, true>(g, bi, bj, smem);
+            gemm_tile<ET, BM, BM, false, true>(g, bi, bj, smem, acc);
+        store_tile<BM, BM, true>(g, bi, bj, acc, smem);
         return;
     }
     tile_coords<false>(item, g.M, g.N, BM, BM, bi, bj);
+    bool done = false;
     if constexpr (ET == OP_F32) {
         if (two_a) {
-            gemm_tile<ET, BM, BM, true, false>(g, bi, bj, smem);
-            return;
+            gemm_tile<ET, BM, BM, true, false>(g, bi, bj, smem, acc);
+            done = true;
         }
     }
-    if (g.direct)
-        gemm_tile_direct<ET, BM, BM, false>(g, bi, bj, smem);
-    else
-        gemm_tile<ET, BM, BM, false, false>(g, bi, bj, smem);
+    if (!done) {
+        if (g.direct)
+            gemm_tile_direct<ET, BM, BM, false>(g, bi, bj, smem, acc);
+        else
+            gemm_tile<ET, BM, BM, false, false>(g, bi, bj, smem, acc);
+    }
+    store_tile<BM, BM, false>(g, bi, bj, acc, smem);
 }
 
 // One item per call, not inlined: each configuration gets its own register

@@ -94,96 +94,149 @@ __device__ __forceinline__ floatx16 mfma_32b(const u32x4 &a0, const u32x4 &a1, c
     return acc;
 }
 
-// Epilogue for one lane's 4 consecutive rows ib..ib+3 of column j:
-// v = alpha acc + beta D (given) + diag [i == j], then the FP32 outputs C/CT
-// and the low-precision copies Clp/CTlp (value * lp_scale).  SYM: only
-// i >= j is kept on diagonal tiles and every kept i != j is also written to
-// the mirrored position [j][i].
-template <bool SYM>
-__device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j, float v[4], bool diag_tile) {
-    bool wr[4], mir[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int i = ib + e;
-        if (i == j) v[e] += g.diag;
-        wr[e] = i < g.M && (!diag_tile || i >= j);
-        mir[e] = SYM && wr[e] && i != j;
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        if (!wr[e]) continue;
-        const int64_t i = ib + e;
-        if (g.C) g.C[i * g.ldc + j] = v[e];
-        if (g.Clp) store_lp(g.Clp, g.lp_type, i * g.ldclp + j, v[e] * g.lp_scale, g.lp_plane);
-    }
-    float *ct = SYM ? g.C : g.CT;
-    const int64_t ldct = SYM ? g.ldc : g.ldct;
-    const int ctv = SYM ? g.c_vec : g.ct_vec;
-    bool t[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) t[e] = SYM ? mir[e] : (ib + e < g.M);
-    if (ct) {
-        float *p = ct + (int64_t)j * ldct + ib;
-        if (ctv && t[0] && t[1] && t[2] && t[3]) {
-            *(floatx4 *)p = floatx4{v[0], v[1], v[2], v[3]};
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (t[e]) p[e] = v[e];
-        }
-    }
-    void *ctl = SYM ? g.Clp : g.CTlp;
-    const int64_t ldctl = SYM ? g.ldclp : g.ldctlp;
-    if (ctl) {
-        const int64_t plane = SYM ? g.lp_plane : g.lp_plane_t;
-        if (t[0] && t[1] && t[2] && t[3]) {
-            store_lp4(ctl, g.lp_type, (int64_t)j * ldctl + ib, v, g.lp_scale, plane);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (t[e]) store_lp(ctl, g.lp_type, (int64_t)j * ldctl + ib + e, v[e] * g.lp_scale, plane);
-        }
-    }
-}
+// ------------------------------------------------------------- epilogue
+// The block's accumulators go through LDS (the operand tiles are no longer
+// needed) and leave in two passes of short loops over 4-element groups:
+//  1. rows: v = alpha acc + beta D + diag [i == j] for 4 consecutive
+//     columns of a row; C and the low-precision copy Clp (row-major), and v
+//     back into LDS;
+//  2. columns (only for CT / CTlp, or the mirrored half of a symmetric
+//     product): v of 4 consecutive rows of a column, written to row j of the
+//     transposed output.
+// SYM: on diagonal tiles only i >= j is kept, and every kept i != j is also
+// written to [j][i].  The values and every output element are those of a
+// lane-by-lane epilogue; the loops keep the code compact (a fully unrolled
+// epilogue of a 256 x 256 tile is several hundred KB of instructions).
+// Tiles of 192 and 256 rows are staged in two halves of rows.
+template <int BM, int BN>
+struct EpiShape {
+    static constexpr int NCH = BM >= 192 ? 2 : 1;  // row chunks
+    static constexpr int RC = BM / NCH;            // rows per chunk
+    static constexpr int P = BN + 8;               // LDS row pitch (floats)
+    static constexpr int BYTES = RC * P * 4;
+    // the register-staged body's LDS (the smallest of any operand type)
+    static_assert(BYTES <= 2 * (BM + BN) * 144, "epilogue staging fits the tile's LDS");
+};
 
-// Scaled accumulators of one block tile -> outputs.  Compile-time loops: the
-// accumulator array must only ever be indexed with constants, or it leaves
-// the register file.
 template <int BM, int BN, bool SYM>
-__device__ __forceinline__ void store_tile(const GemmArgs &g, int bi, int bj, floatx16 (&acc)[BM / 64][BN / 64]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void store_tile(const GemmArgs &g, int bi, int bj, floatx16 (&acc)[BM / 64][BN / 64],
+                                           uint8_t *smem) {
+    static_assert(BM == BN, "square block tiles");
+    typedef EpiShape<BM, BN> E;
+    constexpr int TPR = BN / 4;  // 4-column groups per row
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1, frow = lane & 31, fh = lane >> 5;
     const int i0 = bi * BM, j0 = bj * BN;
     const float alpha = g.alpha * scal(g.sc, g.i_alpha) * g.ab_scale;
     const float beta = g.D ? g.beta * scal(g.sc, g.i_beta) : 0.0f;
     const bool diag_tile = SYM && (bi == bj);
-    static_for<BM / 64>([&](auto a) {
-        // the D values of this row of 32x32 blocks, loaded together so that
-        // their latency is paid once per row rather than once per four rows
-        float dv[BN / 64][16];
-        static_for<BN / 64>([&](auto b) {
-            const int j = j0 + wn * (BN / 2) + b * 32 + frow;
-            static_for<4>([&](auto rg) {
-                const int ib = i0 + wm * (BM / 2) + a * 32 + rg * 8 + fh * 4;
-                static_for<4>([&](auto e) {
-                    const int i = ib + e;
-                    dv[b][rg * 4 + e] = (beta != 0.0f && i < g.M && j < g.N) ? g.D[(int64_t)i * g.ldd + j] : 0.0f;
+    const bool d_vec = ((uintptr_t)g.D & 15) == 0 && g.ldd % 4 == 0;
+    // the transposed outputs: CT / CTlp, or the mirror of a symmetric product
+    float *tc = SYM ? g.C : g.CT;
+    void *tl = SYM ? g.Clp : g.CTlp;
+    const int64_t ldtc = SYM ? g.ldc : g.ldct, ldtl = SYM ? g.ldclp : g.ldctlp;
+    const int64_t tplane = SYM ? g.lp_plane : g.lp_plane_t;
+    const bool tvec = SYM ? g.c_vec : g.ct_vec;
+    float *L = (float *)smem;
+    static_for<E::NCH>([&](auto c) {
+        const int r0 = c * E::RC;  // first tile row of this chunk
+        __syncthreads();           // LDS free: operand tiles (or the previous chunk) consumed
+        if (E::NCH == 1 || wm == c) {
+            static_for<BM / 64>([&](auto a) {
+                static_for<BN / 64>([&](auto b) {
+                    static_for<16>([&](auto r) {
+                        const int row = wm * (BM / 2) + a * 32 + (r / 4) * 8 + fh * 4 + (r % 4) - r0;
+                        const int col = wn * (BN / 2) + b * 32 + frow;
+                        L[row * E::P + col] = acc[a][b][(int)r];
+                    });
                 });
             });
-        });
-        static_for<BN / 64>([&](auto b) {
-            const int j = j0 + wn * (BN / 2) + b * 32 + frow;
-            const bool jok = j < g.N;
-            static_for<4>([&](auto rg) {
-                const int ib = i0 + wm * (BM / 2) + a * 32 + rg * 8 + fh * 4;  // rows ib .. ib+3
+        }
+        __syncthreads();
+        // pass 1: rows
+        for (int q = tid; q < E::RC * TPR; q += 256) {
+            const int lr = q / TPR, lc = (q - lr * TPR) * 4;
+            const int i = i0 + r0 + lr, j = j0 + lc;
+            floatx4 *lp = (floatx4 *)&L[lr * E::P + lc];
+            const floatx4 a4 = *lp;
+            float v[4];
+            bool ok[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                ok[e] = i < g.M && j + e < g.N && (!diag_tile || i >= j + e);
+                v[e] = alpha * a4[e];
+            }
+            if (beta != 0.0f) {
+                const float *dp = g.D + (int64_t)i * g.ldd + j;
+                if (d_vec && i < g.M && j + 3 < g.N) {
+                    const floatx4 d4 = *(const floatx4 *)dp;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] += beta * d4[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] += beta * ((i < g.M && j + e < g.N) ? dp[e] : 0.0f);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (i == j + e) v[e] += g.diag;
+            const bool all = ok[0] && ok[1] && ok[2] && ok[3];
+            if (g.C) {
+                float *cp = g.C + (int64_t)i * g.ldc + j;
+                if (all && g.c_vec) {
+                    *(floatx4 *)cp = floatx4{v[0], v[1], v[2], v[3]};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (ok[e]) cp[e] = v[e];
+                }
+            }
+            if (g.Clp) {
+                if (all) {
+                    store_lp4(g.Clp, g.lp_type, (int64_t)i * g.ldclp + j, v, g.lp_scale, g.lp_plane);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (ok[e]) store_lp(g.Clp, g.lp_type, (int64_t)i * g.ldclp + j + e, v[e] * g.lp_scale, g.lp_plane);
+                }
+            }
+            *lp = floatx4{v[0], v[1], v[2], v[3]};
+        }
+        if (tc || tl) {
+            __syncthreads();
+            // pass 2: columns (4 consecutive rows of column j -> row j of the transposed output)
+            for (int q = tid; q < (E::RC / 4) * BN; q += 256) {
+                const int lg = q / BN, lc = q - lg * BN;
+                const int i = i0 + r0 + lg * 4, j = j0 + lc;
                 float v[4];
-                static_for<4>([&](auto e) {
-                    v[e] = alpha * acc[a][b][rg * 4 + e];
-                    if (beta != 0.0f) v[e] += beta * dv[b][rg * 4 + e];
-                });
-                if (jok) epilogue_store<SYM>(g, ib, j, v, diag_tile);
-            });
-        });
+                bool ok[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = L[(lg * 4 + e) * E::P + lc];
+                    ok[e] = i + e < g.M && j < g.N && (!SYM || !diag_tile || i + e > j);
+                }
+                const bool all = ok[0] && ok[1] && ok[2] && ok[3];
+                if (tc) {
+                    float *p = tc + (int64_t)j * ldtc + i;
+                    if (all && tvec) {
+                        *(floatx4 *)p = floatx4{v[0], v[1], v[2], v[3]};
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (ok[e]) p[e] = v[e];
+                    }
+                }
+                if (tl) {
+                    if (all) {
+                        store_lp4(tl, g.lp_type, (int64_t)j * ldtl + i, v, g.lp_scale, tplane);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (ok[e]) store_lp(tl, g.lp_type, (int64_t)j * ldtl + i + e, v[e] * g.lp_scale, tplane);
+                    }
+                }
+            }
+        }
     });
 }
 
@@ -251,7 +304,8 @@ __device__ __forceinline__ u32x4 load_chunk_masked(const typename Op<ET>::T *P, 
 
 // One BM x BN output tile of the product described by g.
 template <int ET, int BM, int BN, bool TWO_A, bool SYM>
-__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uint8_t *smem) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uint8_t *smem,
+                                          floatx16 (&acc)[BM / 64][BN / 64]) {
     typedef typename Op<ET>::T T;
     constexpr int EPC = Op<ET>::EPC;
     constexpr int BK = 8 * EPC;        // elements per k-tile
@@ -322,7 +376,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uin
         for (int p = 0; p < RB; ++p) *(u32x4 *)&Bs[(lrow + 32 * p) * ROWB + lchunk * 16] = rb[set][p];
     };
 
-    floatx16 acc[TM][TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -383,7 +436,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uin
         }
     }
 
-    store_tile<BM, BN, SYM>(g, bi, bj, acc);
 }
 
 // Products whose k extent is a whole number of k-tiles (and whose operands
@@ -404,7 +456,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
 }
 
 template <int ET, int BM, int BN, bool SYM>
-__device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int bj, uint8_t *smem) {
+__device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int bj, uint8_t *smem,
+                                                 floatx16 (&acc)[BM / 64][BN / 64]) {
     typedef typename Op<ET>::T T;
     constexpr int EPC = Op<ET>::EPC;
     constexpr int ESZ = (int)sizeof(T);
@@ -483,7 +536,6 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
             }
         }
     };
-    floatx16 acc[TM][TN];
 #pragma unroll
     for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -548,7 +600,22 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
-    store_tile<BM, BN, SYM>(g, bi, bj, acc);
+}
+
+// One block tile of a product: the operand body (direct-to-LDS or
+// register-staged, chosen per product) accumulates, then one epilogue.
+template <int ET, int BM, int BN, bool TWO_A, bool SYM>
+__device__ __forceinline__ void gemm_block(const GemmArgs &g, int bi, int bj, uint8_t *smem) {
+    floatx16 acc[BM / 64][BN / 64];
+    bool done = false;
+    if constexpr (!TWO_A) {
+        if (g.direct) {
+            gemm_tile_direct<ET, BM, BN, SYM>(g, bi, bj, smem, acc);
+            done = true;
+        }
+    }
+    if (!done) gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem, acc);
+    store_tile<BM, BN, SYM>(g, bi, bj, acc, smem);
 }
 
 // One product: block b computes local tile xcd_remap(b) (each XCD gets a
@@ -558,13 +625,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_nt(GemmArgs g) {
     __shared__ __attribute__((aligned(16))) uint8_t smem[TileShape<ET, BM, BN>::SMEM];
     int bi, bj;
     tile_coords<SYM>(xcd_remap(blockIdx.x, gridDim.x), g.M, g.N, BM, BN, bi, bj);
-    if constexpr (!TWO_A) {
-        if (g.direct) {
-            gemm_tile_direct<ET, BM, BN, SYM>(g, bi, bj, smem);
-            return;
-        }
-    }
-    gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
+    gemm_block<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
 }
 
 // Many products of one kind in one launch (batched and serving forms):
@@ -588,13 +649,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_grouped(const GemmArgs *args, c
     const GemmArgs g = args[lo];
     int bi, bj;
     tile_coords<SYM>(b - prefix[lo], g.M, g.N, BM, BN, bi, bj);
-    if constexpr (!TWO_A) {
-        if (g.direct) {
-            gemm_tile_direct<ET, BM, BN, SYM>(g, bi, bj, smem);
-            return;
-        }
-    }
-    gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
+    gemm_block<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
 }
 
 // One stage of a device-described batch (psvt_svt_batched): a fixed grid of
@@ -613,14 +668,7 @@ __global__ __launch_bounds__(256, OCC) void gemm_batched(BatchView v, GemmStageT
         relocate_gemm(st, mi, v.op, v.lp, g);
         int bi, bj;
         tile_coords<SYM>(t - v.prefix[i], g.M, g.N, BM, BN, bi, bj);
-        bool done = false;
-        if constexpr (!TWO_A) {
-            if (g.direct) {
-                gemm_tile_direct<ET, BM, BN, SYM>(g, bi, bj, smem);
-                done = true;
-            }
-        }
-        if (!done) gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
+        gemm_block<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
         __syncthreads();  // the next tile refills LDS
     }
 }
