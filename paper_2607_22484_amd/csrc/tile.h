@@ -95,6 +95,115 @@ __device__ __forceinline__ floatx16 mfma_32b(const u32x4 &a0, const u32x4 &a1, c
 }
 
 // ------------------------------------------------------------- epilogue
+// Tiles up to 128 x 128: from the accumulator registers.
+// Epilogue for one lane's 4 consecutive rows ib..ib+3 of column j:
+// v = alpha acc + beta D (given) + diag [i == j], then the FP32 outputs C/CT
+// and the low-precision copies Clp/CTlp (value * lp_scale).  SYM: only
+// i >= j is kept on diagonal tiles and every kept i != j is also written to
+// the mirrored position [j][i].
+template <bool SYM>
+__device__ __forceinline__ void epilogue_store(const GemmArgs &g, int ib, int j, float v[4], bool diag_tile) {
+    bool wr[4], mir[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int i = ib + e;
+        if (i == j) v[e] += g.diag;
+        wr[e] = i < g.M && (!diag_tile || i >= j);
+        mir[e] = SYM && wr[e] && i != j;
+    }
+    if (g.C) {
+        float *p = g.C + (int64_t)ib * g.ldc + j;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (wr[e]) p[(int64_t)e * g.ldc] = v[e];
+    }
+    if (g.Clp) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (wr[e]) store_lp(g.Clp, g.lp_type, (int64_t)(ib + e) * g.ldclp + j, v[e] * g.lp_scale, g.lp_plane);
+    }
+    float *ct = SYM ? g.C : g.CT;
+    const int64_t ldct = SYM ? g.ldc : g.ldct;
+    const int ctv = SYM ? g.c_vec : g.ct_vec;
+    bool t[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[e] = SYM ? mir[e] : (ib + e < g.M);
+    const bool all = t[0] && t[1] && t[2] && t[3];
+    if (ct) {
+        float *p = ct + (int64_t)j * ldct + ib;
+        if (ctv && all) {
+            *(floatx4 *)p = floatx4{v[0], v[1], v[2], v[3]};
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t[e]) p[e] = v[e];
+        }
+    }
+    void *ctl = SYM ? g.Clp : g.CTlp;
+    const int64_t ldctl = SYM ? g.ldclp : g.ldctlp;
+    if (ctl) {
+        const int64_t plane = SYM ? g.lp_plane : g.lp_plane_t;
+        if (all) {
+            store_lp4(ctl, g.lp_type, (int64_t)j * ldctl + ib, v, g.lp_scale, plane);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t[e]) store_lp(ctl, g.lp_type, (int64_t)j * ldctl + ib + e, v[e] * g.lp_scale, plane);
+        }
+    }
+}
+
+// Scaled accumulators of one block tile -> outputs, one 32-row group of
+// the wave's rows at a time.  HAS_D: the D values of row group a + 1 are
+// loaded before the stores of group a, so that waiting for them never waits
+// for those stores (vector memory counters retire in issue order); without
+// D there is no load and no wait between the stores.  Compile-time loops:
+// the accumulator array must only ever be indexed with constants, or it
+// leaves the register file.
+template <int BM, int BN, bool SYM, bool HAS_D>
+__device__ __forceinline__ void store_tile_regs_v(const GemmArgs &g, int bi, int bj,
+                                                  floatx16 (&acc)[BM / 64][BN / 64], float alpha, float beta,
+                                                  const int tid) {
+    constexpr int TM = BM / 64, TN = BN / 64;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1, frow = lane & 31, fh = lane >> 5;
+    const int i0 = bi * BM + wm * (BM / 2), j0 = bj * BN + wn * (BN / 2) + frow;
+    const bool diag_tile = SYM && (bi == bj);
+    float dv[HAS_D ? 2 : 1][TN][16];
+    auto load_d = [&](auto a) {
+        static_for<4>([&](auto rg) {
+            const int ib = i0 + a * 32 + rg * 8 + fh * 4;
+            const float *drow = g.D + (int64_t)ib * g.ldd + j0;
+            static_for<TN>([&](auto b) {
+                const int j = j0 + b * 32;
+                static_for<4>([&](auto e) {
+                    dv[a & 1][b][rg * 4 + e] =
+                        (ib + e < g.M && j < g.N) ? drow[(int64_t)e * g.ldd + b * 32] : 0.0f;
+                });
+            });
+        });
+    };
+    if constexpr (HAS_D) load_d(std::integral_constant<int, 0>{});
+    static_for<TM>([&](auto a) {
+        if constexpr (HAS_D && a + 1 < TM) load_d(std::integral_constant<int, a + 1>{});
+        static_for<TN>([&](auto b) {
+            const int j = j0 + b * 32;
+            const bool jok = j < g.N;
+            static_for<4>([&](auto rg) {
+                const int ib = i0 + a * 32 + rg * 8 + fh * 4;  // rows ib .. ib+3
+                float v[4];
+                static_for<4>([&](auto e) {
+                    v[e] = alpha * acc[a][b][rg * 4 + e];
+                    if constexpr (HAS_D) v[e] += beta * dv[HAS_D ? (a & 1) : 0][b][rg * 4 + e];
+                });
+                if (jok) epilogue_store<SYM>(g, ib, j, v, diag_tile);
+            });
+        });
+    });
+}
+
+// Tiles of 192 and 256: through LDS.
+
 // The block's accumulators go through LDS (the operand tiles are no longer
 // needed) and leave in two passes of short loops over 4-element groups:
 //  1. rows: v = alpha acc + beta D + diag [i == j] for 4 consecutive
@@ -119,12 +228,12 @@ struct EpiShape {
 };
 
 template <int BM, int BN, bool SYM>
-__device__ __forceinline__ void store_tile(const GemmArgs &g, int bi, int bj, floatx16 (&acc)[BM / 64][BN / 64],
-                                           uint8_t *smem) {
+__device__ __forceinline__ void store_tile_lds(const GemmArgs &g, int bi, int bj, floatx16 (&acc)[BM / 64][BN / 64],
+                                               uint8_t *smem, const int tid) {
     static_assert(BM == BN, "square block tiles");
     typedef EpiShape<BM, BN> E;
     constexpr int TPR = BN / 4;  // 4-column groups per row
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1, frow = lane & 31, fh = lane >> 5;
     const int i0 = bi * BM, j0 = bj * BN;
     const float alpha = g.alpha * scal(g.sc, g.i_alpha) * g.ab_scale;
@@ -240,6 +349,25 @@ __device__ __forceinline__ void store_tile(const GemmArgs &g, int bi, int bj, fl
     });
 }
 
+// One epilogue per block tile.  Up to 128 x 128 the per-lane epilogue is
+// a few KB of code; the 192/256 tiles leave through LDS, whose loops keep
+// the kernel within the instruction cache.
+template <int BM, int BN, bool SYM>
+__device__ __forceinline__ void store_tile(const GemmArgs &g, int bi, int bj, floatx16 (&acc)[BM / 64][BN / 64],
+                                           uint8_t *smem, const int tid = (int)threadIdx.x) {
+    if constexpr (BM >= 192) {
+        store_tile_lds<BM, BN, SYM>(g, bi, bj, acc, smem, tid);
+    } else {
+        static_assert(BM == BN, "square block tiles");
+        const float alpha = g.alpha * scal(g.sc, g.i_alpha) * g.ab_scale;
+        const float beta = g.D ? g.beta * scal(g.sc, g.i_beta) : 0.0f;
+        if (beta != 0.0f)
+            store_tile_regs_v<BM, BN, SYM, true>(g, bi, bj, acc, alpha, beta, tid);
+        else
+            store_tile_regs_v<BM, BN, SYM, false>(g, bi, bj, acc, alpha, beta, tid);
+    }
+}
+
 // ------------------------------------------------------------------ GEMM
 
 // BM x BN block tile, 256 threads = 2 x 2 waves, each wave (BM/2) x (BN/2)
@@ -305,7 +433,7 @@ __device__ __forceinline__ u32x4 load_chunk_masked(const typename Op<ET>::T *P, 
 // One BM x BN output tile of the product described by g.
 template <int ET, int BM, int BN, bool TWO_A, bool SYM>
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uint8_t *smem,
-                                          floatx16 (&acc)[BM / 64][BN / 64]) {
+                                          floatx16 (&acc)[BM / 64][BN / 64], const int tid = (int)threadIdx.x) {
     typedef typename Op<ET>::T T;
     constexpr int EPC = Op<ET>::EPC;
     constexpr int BK = 8 * EPC;        // elements per k-tile
@@ -313,7 +441,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bi, int bj, uin
     constexpr int TM = BM / 64, TN = BN / 64;
     constexpr int RA = BM / 32, RB = BN / 32;  // 16-byte loads per thread
     const int i0 = bi * BM, j0 = bj * BN;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
 
     const T *A = (const T *)g.A;
@@ -457,7 +585,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
 
 template <int ET, int BM, int BN, bool SYM>
 __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int bj, uint8_t *smem,
-                                                 floatx16 (&acc)[BM / 64][BN / 64]) {
+                                                 floatx16 (&acc)[BM / 64][BN / 64], const int tid = (int)threadIdx.x) {
     typedef typename Op<ET>::T T;
     constexpr int EPC = Op<ET>::EPC;
     constexpr int ESZ = (int)sizeof(T);
@@ -474,7 +602,7 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
     constexpr int PLANE = (BM + BN) * 128;
     constexpr int STAGE = FUSED ? 2 * PLANE : PLANE;
     const int i0 = bi * BM, j0 = bj * BN;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const uint32_t abytes = (uint32_t)((int64_t)g.M * g.lda * ESZ), bbytes = (uint32_t)((int64_t)g.N * g.ldb * ESZ);
     const __amdgpu_buffer_rsrc_t ra_hi = make_rsrc(g.A, abytes), rb_hi = make_rsrc(g.B, bbytes);
@@ -602,20 +730,48 @@ __device__ __forceinline__ void gemm_tile_direct(const GemmArgs &g, int bi, int 
     }
 }
 
+// Block-uniform values read from memory: every lane reads the same words,
+// and readfirstlane keeps them in scalar registers (the descriptor of a
+// device-described product then costs no vector registers).
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T out;
+    const uint32_t *src = (const uint32_t *)p;
+    uint32_t *dst = (uint32_t *)&out;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return out;
+}
+
+// owner_of (batched.h) with block-uniform control flow.
+__device__ __forceinline__ int owner_of_uniform(const int *prefix, int n, int t) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__builtin_amdgcn_readfirstlane(prefix[mid]) <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // One block tile of a product: the operand body (direct-to-LDS or
 // register-staged, chosen per product) accumulates, then one epilogue.
 template <int ET, int BM, int BN, bool TWO_A, bool SYM>
-__device__ __forceinline__ void gemm_block(const GemmArgs &g, int bi, int bj, uint8_t *smem) {
+__device__ __forceinline__ void gemm_block(const GemmArgs &g, int bi, int bj, uint8_t *smem,
+                                           const int tid = (int)threadIdx.x) {
     floatx16 acc[BM / 64][BN / 64];
     bool done = false;
     if constexpr (!TWO_A) {
         if (g.direct) {
-            gemm_tile_direct<ET, BM, BN, SYM>(g, bi, bj, smem, acc);
+            gemm_tile_direct<ET, BM, BN, SYM>(g, bi, bj, smem, acc, tid);
             done = true;
         }
     }
-    if (!done) gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem, acc);
-    store_tile<BM, BN, SYM>(g, bi, bj, acc, smem);
+    if (!done) gemm_tile<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem, acc, tid);
+    store_tile<BM, BN, SYM>(g, bi, bj, acc, smem, tid);
 }
 
 // One product: block b computes local tile xcd_remap(b) (each XCD gets a
@@ -660,15 +816,20 @@ __global__ __launch_bounds__(256, OCC) void gemm_grouped(const GemmArgs *args, c
 template <int ET, int BM, int BN, int OCC, bool TWO_A, bool SYM>
 __global__ __launch_bounds__(256, OCC) void gemm_batched(BatchView v, GemmStageT st) {
     __shared__ __attribute__((aligned(16))) uint8_t smem[TileShape<ET, BM, BN>::SMEM];
-    const int total = v.prefix[v.count];
+    const int total = __builtin_amdgcn_readfirstlane(v.prefix[v.count]);
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
-        const int i = owner_of(v.prefix, v.count, t);
-        const MatInfo mi = v.mats[i];
+        const int i = owner_of_uniform(v.prefix, v.count, t);
+        const MatInfo mi = uniform_load(&v.mats[i]);
         GemmArgs g;
         relocate_gemm(st, mi, v.op, v.lp, g);
         int bi, bj;
-        tile_coords<SYM>(t - v.prefix[i], g.M, g.N, BM, BN, bi, bj);
-        gemm_block<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem);
+        tile_coords<SYM>(t - __builtin_amdgcn_readfirstlane(v.prefix[i]), g.M, g.N, BM, BN, bi, bj);
+        // the thread index as an opaque value of this iteration: the bodies'
+        // per-thread offsets are then recomputed per tile instead of being
+        // hoisted out of the loop and held in registers across it
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        gemm_block<ET, BM, BN, TWO_A, SYM>(g, bi, bj, smem, tid);
         __syncthreads();  // the next tile refills LDS
     }
 }
