@@ -56,18 +56,17 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the PMC summaries under
-    profiles/ (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy kernel's
-    reading), or None when absent or taken from other kernel sources."""
-    d = os.path.join(ROOT, "profiles")
+def stored_traffic(kernel, n):
+    """HBM bytes per launch of ``kernel`` in the n x n FP32 workload, from
+    its PMC summary under profiles/ (FETCH_SIZE + WRITE_SIZE, each scaled by
+    a plain copy kernel's reading), or None when absent or taken from other
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_svt%d_fp32.txt" % n)
     sha = kernel_source_sha()
-    if not os.path.isdir(d):
+    if not os.path.isfile(path):
         return None
-    for f in sorted(os.listdir(d)):
-        if not f.startswith("traffic_"):
-            continue
-        with open(os.path.join(d, f)) as fh:
+    for f in (path,):
+        with open(f) as fh:
             for line in fh:
                 if not line.startswith("traffic "):
                     continue
@@ -814,7 +813,7 @@ def main():
         "bound": "mfma", "kernel": dom["name"], "launches": dom["launches"], "avg_launch_ms": dom_avg_ms,
         "flops_per_launch": dom["flops"] / dom["launches"],
         "achieved": dom_tflops, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-        "frac": dom_tflops / PEAK_TFLOPS["f32"], "traffic": stored_traffic(dom["name"]),
+        "frac": dom_tflops / PEAK_TFLOPS["f32"], "traffic": stored_traffic(dom["name"], n),
         "kernel_source_sha": kernel_source_sha(),
     }
     kernels = [{"name": t["name"], "launches": t["launches"], "ms_per_step": t["total_ms"] / args.steps,
