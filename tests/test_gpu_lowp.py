@@ -192,6 +192,29 @@ def test_bf16_schedule_svt(gpu_lib, tdev, shape):
     assert err <= TOL_LOWP
 
 
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("sched", [dict(n_bf16=18), dict(n_fp8=6, n_bf16=12)], ids=["bf16", "fp8"])
+def test_lowp_schedules_every_tile(gpu_lib, tdev, sched, tile):
+    """Both low-precision schedules with every tile configuration forced, on
+    a ragged shape in both orientations: the epilogues' low-precision
+    copies (row-major and transposed, split-BF16 planes, FP8 bytes) from the
+    per-lane epilogue (64/128 tiles) and the LDS-staged one (192/256), with
+    partial edge tiles."""
+    torch, dev = tdev
+    pb = _noisy(700, 452, r=32, idx=1)
+    _announce("svt %s tile=%d" % (sched, tile))
+    gpu_lib.force_tile(tile)
+    try:
+        Y = host(gpu_lib.svt(dev_f32(torch, dev, pb.A), pb.tau, iters=20, **sched)).numpy().astype(np.float64)
+        Yw = host(gpu_lib.svt(dev_f32(torch, dev, np.ascontiguousarray(pb.A.T)), pb.tau, iters=20,
+                              **sched)).numpy().astype(np.float64)
+    finally:
+        gpu_lib.force_tile(0)
+    ref = oracle.svt(pb.A, pb.tau)
+    assert oracle.rel_fro_err(Y, ref) <= TOL_LOWP
+    assert oracle.rel_fro_err(Yw, ref.T) <= TOL_LOWP
+
+
 @pytest.mark.parametrize("shape", [(768, 384), (512, 512)])
 def test_fp8_bf16_schedule_svt(gpu_lib, tdev, shape):
     """6 FP8 + 12 BF16 + 2 FP32 iterations (the serving schedule)."""
