@@ -217,15 +217,25 @@ __device__ __forceinline__ void store_tile_regs_v(const GemmArgs &g, int bi, int
 // lane-by-lane epilogue; the loops keep the code compact (a fully unrolled
 // epilogue of a 256 x 256 tile is several hundred KB of instructions).
 // Tiles of 192 and 256 rows are staged in two halves of rows.
+// LDS layout: element (r, c) of a chunk at r * BN + (c ^ swz(r)), swz(r) =
+// 8 ((r / 4) mod 8).  The XOR moves 8-column groups within their 64-column
+// block, so 4-column groups stay contiguous and 16-byte aligned, and:
+//  * a 16-lane phase of pass 1 (16 consecutive 4-column groups of a row)
+//    reads one 64-float block, all banks once;
+//  * pass 2 gives a wave 32 rows x 8 columns: lane (li, lj) holds rows
+//    4 li .. 4 li + 3 of column 8 cg + lj, at bank 8 (cg ^ li) + lj (all
+//    64 banks once per row offset), and the 8 lanes of one column write 128
+//    contiguous bytes of the transposed row.
 template <int BM, int BN>
 struct EpiShape {
     static constexpr int NCH = BM >= 192 ? 2 : 1;  // row chunks
     static constexpr int RC = BM / NCH;            // rows per chunk
-    static constexpr int P = BN + 8;               // LDS row pitch (floats)
-    static constexpr int BYTES = RC * P * 4;
+    static constexpr int BYTES = RC * BN * 4;
+    static_assert(BN % 64 == 0 && RC % 32 == 0, "whole 64-column blocks, 32-row groups");
     // the register-staged body's LDS (the smallest of any operand type)
     static_assert(BYTES <= 2 * (BM + BN) * 144, "epilogue staging fits the tile's LDS");
 };
+__device__ __forceinline__ int epi_idx(int r, int c, int bn) { return r * bn + (c ^ (((r >> 2) & 7) << 3)); }
 
 template <int BM, int BN, bool SYM>
 __device__ __forceinline__ void store_tile_lds(const GemmArgs &g, int bi, int bj, floatx16 (&acc)[BM / 64][BN / 64],
@@ -256,7 +266,7 @@ __device__ __forceinline__ void store_tile_lds(const GemmArgs &g, int bi, int bj
                     static_for<16>([&](auto r) {
                         const int row = wm * (BM / 2) + a * 32 + (r / 4) * 8 + fh * 4 + (r % 4) - r0;
                         const int col = wn * (BN / 2) + b * 32 + frow;
-                        L[row * E::P + col] = acc[a][b][(int)r];
+                        L[epi_idx(row, col, BN)] = acc[a][b][(int)r];
                     });
                 });
             });
@@ -266,7 +276,7 @@ __device__ __forceinline__ void store_tile_lds(const GemmArgs &g, int bi, int bj
         for (int q = tid; q < E::RC * TPR; q += 256) {
             const int lr = q / TPR, lc = (q - lr * TPR) * 4;
             const int i = i0 + r0 + lr, j = j0 + lc;
-            floatx4 *lp = (floatx4 *)&L[lr * E::P + lc];
+            floatx4 *lp = (floatx4 *)&L[epi_idx(lr, lc, BN)];
             const floatx4 a4 = *lp;
             float v[4];
             bool ok[4];
@@ -313,15 +323,18 @@ __device__ __forceinline__ void store_tile_lds(const GemmArgs &g, int bi, int bj
         }
         if (tc || tl) {
             __syncthreads();
-            // pass 2: columns (4 consecutive rows of column j -> row j of the transposed output)
-            for (int q = tid; q < (E::RC / 4) * BN; q += 256) {
-                const int lg = q / BN, lc = q - lg * BN;
-                const int i = i0 + r0 + lg * 4, j = j0 + lc;
+            // pass 2: columns (4 consecutive rows of column j -> row j of
+            // the transposed output); each wave takes 32 rows x 8 columns
+            for (int q = tid; q < E::RC * BN / 4; q += 256) {
+                const int lj = q & 7, li = (q >> 3) & 7, blk = q >> 6;
+                const int rb = blk / (BN / 8), cg = blk - rb * (BN / 8);
+                const int lr = rb * 32 + li * 4, lc = cg * 8 + lj;
+                const int i = i0 + r0 + lr, j = j0 + lc;
                 float v[4];
                 bool ok[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    v[e] = L[(lg * 4 + e) * E::P + lc];
+                    v[e] = L[epi_idx(lr + e, lc, BN)];
                     ok[e] = i + e < g.M && j < g.N && (!SYM || !diag_tile || i + e > j);
                 }
                 const bool all = ok[0] && ok[1] && ok[2] && ok[3];
