@@ -152,7 +152,8 @@ def time_calls(torch, fn, reps):
 def precision_leg(psvt, torch, dev, checks, problems=None):
     """Precision form: BF16 operand iterations (18) + 2 FP32, on rank-200
     signal + noise, 8192 x 4096 and 4096 x 8192 (left-sided); beside it
-    FP32 and all 20 iterations in split bf16 (no FP32 refinement)."""
+    FP32, all 20 iterations in split bf16 (no FP32 refinement), the H-form,
+    plain-BF16 P, and the serving schedule (6 FP8 + 12 BF16 + 2 FP32)."""
     from paper_2607_22484_amd import inputs
     out = {}
     for (m, n) in [(8192, 4096), (4096, 8192)]:
@@ -164,7 +165,9 @@ def precision_leg(psvt, torch, dev, checks, problems=None):
                          ("bf16_plainP", dict(n_bf16=18, flags=psvt.FLAG_PLAIN_P)),
                          ("bf16_hform", dict(n_bf16=18, flags=psvt.FLAG_HFORM)),
                          ("bf16_hform_plainS", dict(n_bf16=18, flags=psvt.FLAG_HFORM | psvt.FLAG_PLAIN_S)),
-                         ("split_bf16_all", dict(n_bf16=20))]:
+                         ("split_bf16_all", dict(n_bf16=20)),
+                         ("fp8", dict(n_fp8=6, n_bf16=12)),
+                         ("fp8_plainP", dict(n_fp8=6, n_bf16=12, flags=psvt.FLAG_PLAIN_P))]:
             cfg, _ = psvt.make_config(iters=20, **kw)
             ws = torch.empty(psvt.workspace_bytes(psvt.OP_SVT, m, n, cfg), dtype=torch.uint8, device=dev)
             ms = time_calls(torch, lambda: psvt.svt(A, pb.tau, iters=20, out=Y, ws=ws, **kw), 3)
